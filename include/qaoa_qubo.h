@@ -1,0 +1,202 @@
+/*
+ * qaoa_qubo.h -- C ABI of the MI355X (gfx950) exact QAOA-for-QUBO statevector engine.
+ *
+ * The engine evaluates, exactly and without shot sampling, the p-layer QAOA
+ * training objective of the paper "A Distributed Quantum Approximate
+ * Optimization Algorithm Simulator for Engineering Design Optimization":
+ *
+ *   input form        F(z) = c0 + f^T z + z^T H z                       eq. (2)
+ *   canonical form    l_i = f_i + H_ii,  b_ij = H_ij + H_ji (i < j)      eq. (4)-(6)
+ *   cost unitary      U_C(gamma) = exp(-i gamma H_C), H_C|z> = F(z)|z>   eq. (8), (10)
+ *   mixer             U_M(beta) = exp(-i beta sum_q X_q) = prod_q RX_q(2 beta)   eq. (12)-(13)
+ *   state             U_M(b_p)U_C(g_p)...U_M(b_1)U_C(g_1)|+>^n           eq. (11)
+ *   objective         J(x) = sum_z P_x(z) F(z)                           eq. (15), (17)
+ *   parameters        x = [gamma_1, beta_1, ..., gamma_p, beta_p]        (training-objective section)
+ *   local/cross rule  coupling b_ij is local iff q(i) = q(j)             eq. (16)
+ *
+ * Conventions: variable z_i (i = 1..n) is qubit i-1 = bit (i-1) of a basis
+ * index; a printed logical bitstring is z_1 ... z_n (the decoding section's
+ * reversal of the little-endian display).  Gradients are returned in the
+ * same interleaved layout as x.
+ *
+ * General rules for every call:
+ *  - Every call returns a qq_status and never throws.  On error nothing is
+ *    written to the outputs and qq_last_error() describes the cause.
+ *  - The caller owns every array it passes.  qq_problem_create copies H and f.
+ *  - Host arrays are plain C arrays.  Device arrays (selected by the
+ *    QQ_PARAMS_ON_DEVICE / QQ_OUT_ON_DEVICE flags, or documented as device
+ *    pointers) must live on the problem's device.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls that write
+ *    host outputs synchronise that stream before returning; calls whose
+ *    outputs are on the device are asynchronous on it.
+ *  - Input validation (sizes, finiteness, allocation rules) runs on the host
+ *    before any device work.
+ */
+#ifndef QAOA_QUBO_H
+#define QAOA_QUBO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QQ_OK = 0,
+    QQ_E_INVALID = -1,      /* bad argument: size, pointer, non-finite value, unknown flag */
+    QQ_E_ALLOCATION = -2,   /* variable-to-QPU allocation violates the validation rules */
+    QQ_E_TOO_LARGE = -3,    /* the request cannot fit in device memory (decided before allocating) */
+    QQ_E_WORKSPACE = -4,    /* caller workspace smaller than qq_workspace_size() */
+    QQ_E_DEVICE = -5,       /* a HIP runtime call failed (message carries the HIP error string) */
+    QQ_E_NOMEM = -6,        /* a device or host allocation failed */
+    QQ_E_UNSUPPORTED = -7   /* valid request this build does not support (message says which) */
+} qq_status;
+
+/* Flags for the evaluation calls (bitwise OR). */
+enum {
+    QQ_ENERGY = 1,            /* compute J(x) */
+    QQ_GRAD = 2,              /* also compute dJ/dx by the adjoint sweep (implies QQ_ENERGY) */
+    QQ_PARTITIONED = 4,       /* apply the cost layer as per-QPU local phases then the cross phase */
+    QQ_C128 = 8,              /* complex128 state (default complex64) */
+    QQ_PARAMS_ON_DEVICE = 16, /* params pointer is device memory */
+    QQ_OUT_ON_DEVICE = 32     /* output pointers are device memory (no synchronisation) */
+};
+
+#define QQ_MAX_N 34
+#define QQ_MAX_P 64
+#define QQ_MAX_QPUS 16
+#define QQ_MAX_TOPK 16
+
+typedef struct qq_problem qq_problem; /* opaque handle */
+
+typedef struct {
+    int n;                    /* number of binary variables = qubits */
+    int is_integer;           /* 1: C(z) is exact integer arithmetic (H, f, c0 integral, sum of |coefficients| < 2^31) */
+    int diag_bytes;           /* bytes per stored diagonal entry: 2 or 4 (integer), 8 (FP64) */
+    int num_qpus;             /* 0 when no allocation is set */
+    double c0;                /* constant term of eq. (2) */
+    double alpha;             /* identity coefficient of eq. (9) = mean of C over all z */
+    double sigma_c;           /* sqrt(sum h_i^2 + sum J_ij^2) = standard deviation of C over all z */
+    double cmin, cmax;        /* min / max of C(z) over all z */
+    uint64_t argmin_index;    /* lowest basis index attaining cmin (the brute-force optimum) */
+    int64_t nonzero_couplings;/* number of b_ij != 0, i < j */
+    int64_t cross_terms;      /* number of cross-QPU couplings (eq. (16)), -1 without an allocation */
+} qq_info;
+
+/* Thread-local description of the last error on this thread; valid until the next qq_* call. */
+const char *qq_last_error(void);
+
+/* ABI version of this header (increments on incompatible changes). */
+int qq_abi_version(void);
+
+/* Number of visible HIP devices (0 without a GPU). */
+qq_status qq_device_count(int *count);
+
+/*
+ * Create a problem from the dense input form of eq. (2).
+ *   n       number of variables, 1 <= n <= QQ_MAX_N
+ *   H       n*n row-major host array (any, not necessarily symmetric); copied
+ *   f       n host array or NULL (= 0); copied
+ *   c0      constant term
+ *   device  HIP device ordinal
+ * The handle canonicalises (eq. (4)-(5)), classifies the problem as integer
+ * or real, and builds the cost diagonal C(z) of eq. (6) on the device once
+ * (the "build once, bind many" reuse of the circuit-reuse section).
+ * Errors: QQ_E_INVALID (n out of range, NULL H/out, non-finite entry),
+ * QQ_E_TOO_LARGE (the diagonal does not fit the device), QQ_E_DEVICE, QQ_E_NOMEM.
+ */
+qq_status qq_problem_create(int n, const double *H, const double *f, double c0, int device, void *stream,
+                            qq_problem **out);
+
+qq_status qq_problem_destroy(qq_problem *prob);
+
+/* Summary of the problem (see qq_info).  Host call; no device work. */
+qq_status qq_problem_info(const qq_problem *prob, qq_info *out);
+
+/*
+ * Canonical coefficients (eq. (4)-(5)) and the Pauli coefficients of eq. (9):
+ *   ell[n], b[n*n] (row-major, strict upper triangle set, rest 0),
+ *   alpha, h[n], J[n*n] (strict upper triangle), each may be NULL.
+ * alpha = c0 + sum l/2 + sum b/4;  h_i = -l_i/2 - sum_{j != i} b_ij/4;  J_ij = b_ij/4.
+ */
+qq_status qq_coefficients(const qq_problem *prob, double *ell, double *b, double *alpha, double *h, double *J);
+
+/*
+ * Copy the cost diagonal C(z), z = 0..2^n-1 (eq. (6)), to `out`:
+ * int32 entries for integer problems (info.is_integer), double otherwise.
+ * For real problems every entry is c0 + l_i (ascending i) + b_ij (row-major)
+ * summed in FP64 in exactly that order over the set bits of z.
+ * flags: QQ_OUT_ON_DEVICE selects a device `out`.
+ */
+qq_status qq_cost_diagonal(const qq_problem *prob, void *out, int flags, void *stream);
+
+/*
+ * Attach a variable-to-QPU allocation (allocation section; eq. (16)).
+ *   num_qpus      M, 1 <= M <= QQ_MAX_QPUS
+ *   qpu_of_var    n host ints in [0, M): variable i+1 sits on QPU qpu_of_var[i]
+ *   capacities    M host ints or NULL (no capacity limit)
+ * Validation: every entry in range, no QPU over capacity, every QPU used.
+ * Builds, on the device, the per-QPU local cost tables (each indexed by the
+ * QPU's own variables; c0 goes to QPU 0) and the cross-QPU diagonal used by
+ * QQ_PARTITIONED evaluations.  Outputs (each may be NULL): the number of
+ * cross-QPU couplings (nonzero b_ij with q(i) != q(j)) and the per-layer
+ * remote-CNOT estimate 2 * cross (multiply by p for a whole circuit).
+ * Errors: QQ_E_INVALID, QQ_E_ALLOCATION, QQ_E_DEVICE, QQ_E_NOMEM.
+ */
+qq_status qq_set_allocation(qq_problem *prob, int num_qpus, const int32_t *qpu_of_var, const int32_t *capacities,
+                            int64_t *cross_terms_out, int64_t *remote_cx_per_layer_out);
+
+/* Device bytes qq_evaluate needs for (p, batch, flags). */
+qq_status qq_workspace_size(const qq_problem *prob, int p, int batch, int flags, size_t *bytes);
+
+/*
+ * Exact J(x) (eq. (17)) and, with QQ_GRAD, dJ/dx for `batch` parameter sets.
+ *   params      batch x 2p doubles, interleaved [g1, b1, ..., gp, bp] per set
+ *   workspace   device buffer of ws_bytes >= qq_workspace_size(), or NULL to
+ *               let the library allocate (and free) one for this call
+ *   energy_out  batch doubles
+ *   grad_out    batch x 2p doubles (required with QQ_GRAD, else ignored; may be NULL)
+ * The state is complex64 unless QQ_C128; the cost diagonal, the phase
+ * argument reduction and every energy/gradient accumulator are FP64.
+ * Deterministic: identical inputs give bit-identical outputs.
+ * Errors: QQ_E_INVALID (p, batch, non-finite params, missing outputs),
+ * QQ_E_ALLOCATION (QQ_PARTITIONED without an allocation), QQ_E_WORKSPACE,
+ * QQ_E_TOO_LARGE, QQ_E_DEVICE.
+ */
+qq_status qq_evaluate(qq_problem *prob, int p, int batch, const double *params, int flags, void *workspace,
+                      size_t ws_bytes, void *stream, double *energy_out, double *grad_out);
+
+/*
+ * The final state |gamma, beta> of eq. (11) for one parameter set (2p doubles).
+ * psi_out: 2^n complex64 (interleaved float re, im) or, with QQ_C128,
+ * complex128; host memory unless QQ_OUT_ON_DEVICE.
+ */
+qq_status qq_state(qq_problem *prob, int p, const double *params, int flags, void *psi_out, void *stream);
+
+/* Measurement distribution P_x(z) = |<z|gamma,beta>|^2 (eq. (15)) as 2^n doubles. */
+qq_status qq_probabilities(qq_problem *prob, int p, const double *params, int flags, double *prob_out,
+                           void *stream);
+
+/*
+ * The k most probable bitstrings (the elite top-k of the metrics section),
+ * ordered by decreasing probability, ties to the lower basis index.
+ *   k <= QQ_MAX_TOPK; idx_out/prob_out/cost_out: k entries each (cost_out may be NULL).
+ */
+qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int k, uint64_t *idx_out,
+                  double *prob_out, double *cost_out, void *stream);
+
+/*
+ * Measurement baseline: the plain complex128 form with one kernel per gate
+ * (one phase kernel per layer, one RX kernel per qubit and layer, an energy
+ * reduction, and the same adjoint equations unfused), one parameter set per
+ * call, no batching.  Same outputs as qq_evaluate with batch = 1.
+ */
+qq_status qq_evaluate_plain(qq_problem *prob, int p, const double *params, int flags, void *stream,
+                            double *energy_out, double *grad_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAOA_QUBO_H */

@@ -1,0 +1,958 @@
+// qq_api.cpp -- host side of the C ABI declared in include/qaoa_qubo.h.
+//
+// Responsibilities: argument validation (before any device work), the
+// canonical form of eq. (4)-(5), integer classification, the Pauli
+// coefficients of eq. (9), device buffers of the problem handle, the pass
+// planner that turns (n, p, mode) into a sequence of fused tile passes, and
+// the evaluation entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qq_internal.h"
+
+using namespace qq;
+
+namespace {
+
+thread_local std::string g_err;
+
+qq_status fail(qq_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define QQ_HIP(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(QQ_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr double kTwo31 = 2147483648.0;
+constexpr double kTwo15 = 32768.0;
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+int diag_bytes_of(int t) { return t == DIAG_F64 ? 8 : t == DIAG_I32 ? 4 : 2; }
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct qq_problem {
+    int n = 0;
+    int device = 0;
+    uint64_t dim = 0;
+    std::vector<double> H, f;
+    double c0 = 0.0;
+    std::vector<double> ell;  // n
+    std::vector<double> b;    // n*n, strict upper triangle
+    bool is_integer = false;
+    int diag_type = DIAG_F64;
+    int32_t c0_i = 0;
+    std::vector<int32_t> ell_i;
+    // nonzero couplings in row-major order
+    std::vector<int32_t> pair_ij;
+    std::vector<double> pair_b;
+    std::vector<int32_t> pair_bi;
+    // device copies
+    void *d_diag = nullptr;
+    double *d_ell = nullptr;
+    int32_t *d_ell_i = nullptr;
+    int32_t *d_pair_ij = nullptr;
+    double *d_pair_b = nullptr;
+    int32_t *d_pair_bi = nullptr;
+    // summary
+    double alpha = 0, sigma_c = 0, cmin = 0, cmax = 0;
+    uint64_t argmin = 0;
+    // allocation / partitioned phases
+    int num_qpus = 0;
+    std::vector<int32_t> qpu;
+    int64_t cross_terms = -1;
+    int32_t *d_qpu = nullptr;
+    void *d_tables = nullptr;
+    void *d_cross = nullptr;
+    PartDesc *d_part = nullptr;
+
+    ~qq_problem()
+    {
+        void *ptrs[] = {d_diag, d_ell, d_ell_i, d_pair_ij, d_pair_b, d_pair_bi, d_qpu, d_tables, d_cross, d_part};
+        if (dim) (void)hipSetDevice(device);
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+// ---- pass planning -------------------------------------------------------------------------
+// Qubit sets mixed by one pass.  Set 0 is qubits 0..11 (a contiguous tile);
+// each further set is up to 8 qubits placed in the upper 8 bits of a high
+// tile whose low 4 bits are qubits 0..3.
+struct SetDesc {
+    int high;
+    int pos4;
+    int hshift;
+    uint16_t active;
+};
+
+std::vector<SetDesc> make_sets(int n)
+{
+    std::vector<SetDesc> sets;
+    if (n <= kTileBits) {
+        sets.push_back({0, 4, 0, (uint16_t)((1u << n) - 1u)});
+        return sets;
+    }
+    sets.push_back({0, 4, 0, 0x0fff});
+    for (int q0 = kTileBits; q0 < n; q0 += 8) {
+        const int q1 = std::min(n, q0 + 8);
+        const int h = std::min(q0, n - 8);
+        uint16_t act = 0;
+        for (int q = q0; q < q1; ++q) act |= (uint16_t)(1u << (4 + q - h));
+        sets.push_back({1, h, h - 4, act});
+    }
+    return sets;
+}
+
+struct PassPlan {
+    int set = 0;
+    uint32_t flags = 0;
+    int nstates = 1;
+    std::vector<Op> ops;
+    std::vector<int> slot_out;  // local slot -> output index
+};
+
+struct Plan {
+    std::vector<SetDesc> sets;
+    std::vector<PassPlan> passes;
+    int nslots = 0;
+};
+
+enum PlanMode { PM_ENERGY = 1, PM_GRAD = 2, PM_STORE = 4, PM_PART = 8 };
+
+int out_energy() { return 0; }
+int out_gamma(int k) { return 1 + 2 * k; }
+int out_beta(int k) { return 2 + 2 * k; }
+
+int local_slot(PassPlan &pp, int out)
+{
+    for (size_t s = 0; s < pp.slot_out.size(); ++s)
+        if (pp.slot_out[s] == out) return (int)s;
+    pp.slot_out.push_back(out);
+    return (int)pp.slot_out.size() - 1;
+}
+
+Op op_mix(PassPlan &pp, int k, bool inverse, uint16_t active, int states, int out)
+{
+    Op o{};
+    o.kind = OP_MIX;
+    o.layer = (uint8_t)k;
+    o.states = (uint8_t)states;
+    o.flags = inverse ? OPF_INVERSE : 0;
+    o.active = active;
+    o.slot = (uint8_t)(out >= 0 ? local_slot(pp, out) : kNoSlot);
+    return o;
+}
+
+Op op_phase(int k, bool inverse, int states, bool part)
+{
+    Op o{};
+    o.kind = OP_PHASE;
+    o.layer = (uint8_t)k;
+    o.states = (uint8_t)states;
+    o.flags = (uint8_t)((inverse ? OPF_INVERSE : 0) | (part ? OPF_PARTITIONED : 0));
+    o.slot = kNoSlot;
+    return o;
+}
+
+Op op_acc(PassPlan &pp, uint8_t kind, int k, int out, uint8_t flags)
+{
+    Op o{};
+    o.kind = kind;
+    o.layer = (uint8_t)k;
+    o.states = 3;
+    o.flags = flags;
+    o.slot = (uint8_t)local_slot(pp, out);
+    return o;
+}
+
+// Passes for one evaluation.  Layer k (0-based) visits the qubit sets in
+// ascending order when k is even and descending when k is odd ("zig-zag"),
+// so the last set of layer k is the first set of layer k+1: that pass mixes
+// layer k on the set, applies phase k+1 and mixes layer k+1 on the same set.
+// A forward evaluation with s sets takes 1 + p(s-1) passes.  The adjoint
+// sweep runs the same zig-zag backwards over (psi, lambda).
+Plan make_plan(int n, int p, int mode)
+{
+    Plan plan;
+    plan.sets = make_sets(n);
+    const int s = (int)plan.sets.size();
+    const bool grad = mode & PM_GRAD, energy = mode & (PM_ENERGY | PM_GRAD), store = mode & PM_STORE,
+               part = mode & PM_PART;
+    auto order = [&](int k) {
+        std::vector<int> o(s);
+        for (int i = 0; i < s; ++i) o[i] = (k % 2 == 0) ? i : s - 1 - i;
+        return o;
+    };
+    auto act = [&](int set) { return plan.sets[set].active; };
+
+    if (s == 1) {
+        PassPlan pp;
+        pp.set = 0;
+        pp.flags = PF_INIT | (store ? PF_STORE_PSI : 0);
+        pp.nstates = grad ? 2 : 1;
+        for (int k = 0; k < p; ++k) {
+            pp.ops.push_back(op_phase(k, false, 1, part));
+            pp.ops.push_back(op_mix(pp, k, false, act(0), 1, -1));
+        }
+        if (grad) {
+            pp.ops.push_back(op_acc(pp, OP_ENERGY_LAMBDA, p - 1, out_energy(), 0));
+            for (int k = p - 1; k >= 0; --k) {
+                pp.ops.push_back(op_mix(pp, k, true, act(0), 3, out_beta(k)));
+                pp.ops.push_back(op_acc(pp, OP_GGAMMA, k, out_gamma(k),
+                                        (uint8_t)((k > 0 ? OPF_UNPHASE : 0) | (part ? OPF_PARTITIONED : 0))));
+            }
+        } else if (energy) {
+            pp.ops.push_back(op_acc(pp, OP_ENERGY, p - 1, out_energy(), 0));
+        }
+        plan.passes.push_back(pp);
+    } else {
+        {
+            PassPlan pp;
+            pp.set = order(0)[0];
+            pp.flags = PF_INIT | PF_STORE_PSI;
+            pp.ops.push_back(op_phase(0, false, 1, part));
+            pp.ops.push_back(op_mix(pp, 0, false, act(pp.set), 1, -1));
+            plan.passes.push_back(pp);
+        }
+        for (int k = 0; k < p; ++k) {
+            const auto o = order(k);
+            for (int idx = 1; idx < s; ++idx) {
+                const int set = o[idx];
+                PassPlan pp;
+                pp.set = set;
+                if (idx < s - 1) {
+                    pp.flags = PF_LOAD_PSI | PF_STORE_PSI;
+                    pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
+                } else if (k < p - 1) {
+                    pp.flags = PF_LOAD_PSI | PF_STORE_PSI;
+                    pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
+                    pp.ops.push_back(op_phase(k + 1, false, 1, part));
+                    pp.ops.push_back(op_mix(pp, k + 1, false, act(set), 1, -1));
+                } else if (grad) {
+                    // psi in memory stays the state before this set's mixer; lambda is
+                    // formed in registers and leaves with the set already un-mixed.
+                    pp.flags = PF_LOAD_PSI | PF_STORE_LAM;
+                    pp.nstates = 2;
+                    pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
+                    pp.ops.push_back(op_acc(pp, OP_ENERGY_LAMBDA, k, out_energy(), 0));
+                    pp.ops.push_back(op_mix(pp, k, true, act(set), 3, out_beta(k)));
+                } else {
+                    pp.flags = PF_LOAD_PSI | (store ? PF_STORE_PSI : 0);
+                    pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
+                    if (energy) pp.ops.push_back(op_acc(pp, OP_ENERGY, k, out_energy(), 0));
+                }
+                plan.passes.push_back(pp);
+            }
+        }
+        if (grad) {
+            for (int k = p - 1; k >= 0; --k) {
+                auto r = order(k);
+                std::reverse(r.begin(), r.end());
+                for (int idx = 1; idx < s; ++idx) {
+                    const int set = r[idx];
+                    PassPlan pp;
+                    pp.set = set;
+                    pp.nstates = 2;
+                    if (idx < s - 1) {
+                        pp.flags = PF_LOAD_PSI | PF_LOAD_LAM | PF_STORE_PSI | PF_STORE_LAM;
+                        pp.ops.push_back(op_mix(pp, k, true, act(set), 3, out_beta(k)));
+                    } else if (k > 0) {
+                        pp.flags = PF_LOAD_PSI | PF_LOAD_LAM | PF_STORE_PSI | PF_STORE_LAM;
+                        pp.ops.push_back(op_mix(pp, k, true, act(set), 3, out_beta(k)));
+                        pp.ops.push_back(op_acc(pp, OP_GGAMMA, k, out_gamma(k),
+                                                (uint8_t)(OPF_UNPHASE | (part ? OPF_PARTITIONED : 0))));
+                        pp.ops.push_back(op_mix(pp, k - 1, true, act(set), 3, out_beta(k - 1)));
+                    } else {
+                        pp.flags = PF_LOAD_PSI | PF_LOAD_LAM;
+                        pp.ops.push_back(op_mix(pp, 0, true, act(set), 3, out_beta(0)));
+                        pp.ops.push_back(op_acc(pp, OP_GGAMMA, 0, out_gamma(0), 0));
+                    }
+                    plan.passes.push_back(pp);
+                }
+            }
+        }
+    }
+    for (auto &pp : plan.passes) plan.nslots += (int)pp.slot_out.size();
+    return plan;
+}
+
+uint64_t tiles_per_state(int n) { return n <= kTileBits ? 1ull : (1ull << (n - kTileBits)); }
+
+int choose_G(int n, int B)
+{
+    const uint64_t T = tiles_per_state(n);
+    uint64_t target = std::max<uint64_t>(1, 4096 / (uint64_t)B);
+    uint64_t G = 1;
+    while (G * 2 <= target && G * 2 <= T) G *= 2;
+    return (int)G;
+}
+
+struct Layout {
+    size_t psi = 0, lam = 0, partial = 0, params = 0, out = 0, total = 0;
+    int G = 1;
+    int nslots = 0;
+};
+
+Layout make_layout(const qq_problem *pb, int p, int B, int flags, const Plan &plan)
+{
+    Layout L;
+    const size_t es = (flags & QQ_C128) ? 16 : 8;
+    const size_t state = (size_t)pb->dim * es * (size_t)B;
+    const bool grad = flags & QQ_GRAD;
+    const bool multi = plan.sets.size() > 1;
+    L.G = choose_G(pb->n, B);
+    L.nslots = plan.nslots;
+    size_t off = 0;
+    L.psi = off;
+    off += align_up(state);  // also used by qq_state for a single-pass plan
+    L.lam = off;
+    if (grad && multi) off += align_up(state);
+    L.partial = off;
+    off += align_up((size_t)std::max(1, plan.nslots) * B * L.G * sizeof(double));
+    L.params = off;
+    off += align_up((size_t)B * 2 * p * sizeof(double));
+    L.out = off;
+    off += align_up((size_t)B * (1 + 2 * p) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int plan_mode(int flags, bool store)
+{
+    int m = 0;
+    if (flags & QQ_ENERGY) m |= PM_ENERGY;
+    if (flags & QQ_GRAD) m |= PM_GRAD | PM_ENERGY;
+    if (flags & QQ_PARTITIONED) m |= PM_PART;
+    if (store) m |= PM_STORE;
+    return m;
+}
+
+qq_status check_params_host(const double *params, size_t count)
+{
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(params[i])) return fail(QQ_E_INVALID, "params[%zu] is not finite", i);
+    return QQ_OK;
+}
+
+qq_status check_device_fits(int device, size_t bytes, const char *what)
+{
+    size_t freeb = 0, totalb = 0;
+    QQ_HIP(hipSetDevice(device));
+    QQ_HIP(hipMemGetInfo(&freeb, &totalb));
+    if (bytes > totalb)
+        return fail(QQ_E_TOO_LARGE, "%s needs %zu bytes; the device has %zu in total", what, bytes, totalb);
+    return QQ_OK;
+}
+
+// Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
+qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int B, int flags, char *ws,
+                   const double *d_params, hipStream_t stream)
+{
+    const bool c128 = flags & QQ_C128;
+    const uint64_t T = tiles_per_state(pb->n);
+    const size_t es = c128 ? 16 : 8;
+    (void)es;
+    if (plan.nslots > kMaxSlots) return fail(QQ_E_UNSUPPORTED, "plan needs %d accumulator slots (max %d)", plan.nslots, kMaxSlots);
+    int slot_base = 0;
+    for (const auto &pp : plan.passes) {
+        if ((int)pp.ops.size() > kMaxOps) return fail(QQ_E_UNSUPPORTED, "pass has %zu ops (max %d)", pp.ops.size(), kMaxOps);
+        const SetDesc &sd = plan.sets[pp.set];
+        PassArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.n = pb->n;
+        a.p = p;
+        a.B = B;
+        a.G = L.G;
+        a.tiles = T;
+        a.dim_mask = pb->dim - 1;
+        a.pos4 = sd.pos4;
+        a.pos8 = sd.pos4 + 4;
+        a.high = sd.high;
+        a.hshift = sd.hshift;
+        a.flags = pp.flags;
+        a.nops = (int)pp.ops.size();
+        a.nslots = (int)pp.slot_out.size();
+        a.slot_base = slot_base;
+        a.slot_stride = B * L.G;
+        a.amp0 = 1.0 / std::sqrt((double)pb->dim);
+        a.params = d_params;
+        a.diag = pb->d_diag;
+        a.psi = ws + L.psi;
+        a.lam = ws + L.lam;
+        a.state_stride = pb->dim;
+        a.partial = reinterpret_cast<double *>(ws + L.partial);
+        a.part_tables = pb->d_tables;
+        a.cross_diag = pb->d_cross;
+        a.part = pb->d_part;
+        for (size_t i = 0; i < pp.ops.size(); ++i) a.ops[i] = pp.ops[i];
+        QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
+        slot_base += a.nslots;
+    }
+    FinalizeArgs fa;
+    std::memset(&fa, 0, sizeof fa);
+    fa.B = B;
+    fa.G = L.G;
+    fa.p = p;
+    fa.nslots = plan.nslots;
+    fa.escale = pb->n < kTileBits ? std::ldexp(1.0, pb->n - kTileBits) : 1.0;
+    fa.partial = reinterpret_cast<const double *>(ws + L.partial);
+    fa.out = reinterpret_cast<double *>(ws + L.out);
+    int s = 0;
+    for (const auto &pp : plan.passes)
+        for (int o : pp.slot_out) fa.slot_out[s++] = (uint16_t)o;
+    QQ_HIP(launch_finalize(fa, stream));
+    return QQ_OK;
+}
+
+qq_status validate_eval(const qq_problem *pb, int p, int batch, int flags)
+{
+    if (!pb) return fail(QQ_E_INVALID, "problem is NULL");
+    if (p < 1 || p > QQ_MAX_P) return fail(QQ_E_INVALID, "p = %d outside [1, %d]", p, QQ_MAX_P);
+    if (batch < 1) return fail(QQ_E_INVALID, "batch = %d must be >= 1", batch);
+    const int known = QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED | QQ_C128 | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE;
+    if (flags & ~known) return fail(QQ_E_INVALID, "unknown flag bits 0x%x", flags & ~known);
+    if ((flags & QQ_PARTITIONED) && pb->num_qpus == 0)
+        return fail(QQ_E_ALLOCATION, "QQ_PARTITIONED requested but no allocation is set (qq_set_allocation)");
+    return QQ_OK;
+}
+
+// Evaluate a plan for `batch` parameter sets into ws; leaves results at ws + L.out on the device.
+qq_status eval_core(qq_problem *pb, int p, int batch, const double *params, int flags, const Plan &plan,
+                    const Layout &L, char *ws, hipStream_t stream)
+{
+    const double *d_params = params;
+    if (!(flags & QQ_PARAMS_ON_DEVICE)) {
+        d_params = reinterpret_cast<const double *>(ws + L.params);
+        QQ_HIP(hipMemcpyAsync(ws + L.params, params, (size_t)batch * 2 * p * sizeof(double), hipMemcpyHostToDevice,
+                              stream));
+    }
+    return run_plan(pb, plan, L, p, batch, flags, ws, d_params, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qq_last_error(void) { return g_err.c_str(); }
+
+int qq_abi_version(void) { return 1; }
+
+qq_status qq_device_count(int *count)
+{
+    if (!count) return fail(QQ_E_INVALID, "count is NULL");
+    int c = 0;
+    hipError_t e = hipGetDeviceCount(&c);
+    if (e != hipSuccess) c = 0;
+    *count = c;
+    return QQ_OK;
+}
+
+qq_status qq_problem_create(int n, const double *H, const double *f, double c0, int device, void *stream_,
+                            qq_problem **out)
+{
+    g_err.clear();
+    if (!out) return fail(QQ_E_INVALID, "out is NULL");
+    if (n < 1 || n > QQ_MAX_N) return fail(QQ_E_INVALID, "n = %d outside [1, %d]", n, QQ_MAX_N);
+    if (!H) return fail(QQ_E_INVALID, "H is NULL");
+    if (!std::isfinite(c0)) return fail(QQ_E_INVALID, "c0 is not finite");
+    for (int i = 0; i < n * n; ++i)
+        if (!std::isfinite(H[i])) return fail(QQ_E_INVALID, "H[%d][%d] is not finite", i / n, i % n);
+    if (f)
+        for (int i = 0; i < n; ++i)
+            if (!std::isfinite(f[i])) return fail(QQ_E_INVALID, "f[%d] is not finite", i);
+    if (device < 0) return fail(QQ_E_INVALID, "device = %d", device);
+
+    qq_problem *pb = new (std::nothrow) qq_problem();
+    if (!pb) return fail(QQ_E_NOMEM, "host allocation failed");
+    std::unique_ptr<qq_problem> guard(pb);
+    pb->n = n;
+    pb->device = device;
+    pb->H.assign(H, H + (size_t)n * n);
+    pb->f.assign(n, 0.0);
+    if (f) pb->f.assign(f, f + n);
+    pb->c0 = c0;
+
+    // eq. (4)-(5)
+    pb->ell.assign(n, 0.0);
+    pb->b.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) pb->ell[i] = pb->f[i] + pb->H[(size_t)i * n + i];
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) pb->b[(size_t)i * n + j] = pb->H[(size_t)i * n + j] + pb->H[(size_t)j * n + i];
+
+    // integer classification: integral inputs whose canonical magnitudes sum below 2^31
+    bool integral = std::nearbyint(c0) == c0;
+    for (double v : pb->H) integral = integral && std::nearbyint(v) == v;
+    for (double v : pb->f) integral = integral && std::nearbyint(v) == v;
+    double mag = std::fabs(c0);
+    for (double v : pb->ell) mag += std::fabs(v);
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) mag += std::fabs(pb->b[(size_t)i * n + j]);
+    pb->is_integer = integral && mag < kTwo31;
+    pb->diag_type = !pb->is_integer ? DIAG_F64 : (mag < kTwo15 ? DIAG_I16 : DIAG_I32);
+    pb->c0_i = pb->is_integer ? (int32_t)c0 : 0;
+    pb->ell_i.assign(n, 0);
+    if (pb->is_integer)
+        for (int i = 0; i < n; ++i) pb->ell_i[i] = (int32_t)pb->ell[i];
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double v = pb->b[(size_t)i * n + j];
+            if (v == 0.0) continue;
+            pb->pair_ij.push_back(i);
+            pb->pair_ij.push_back(j);
+            pb->pair_b.push_back(v);
+            pb->pair_bi.push_back(pb->is_integer ? (int32_t)v : 0);
+        }
+
+    // Pauli coefficients of eq. (9) and the spread of C
+    {
+        double alpha = c0, s2 = 0.0;
+        std::vector<double> h(n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            alpha += pb->ell[i] / 2.0;
+            h[i] -= pb->ell[i] / 2.0;
+        }
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                const double v = pb->b[(size_t)i * n + j];
+                alpha += v / 4.0;
+                h[i] -= v / 4.0;
+                h[j] -= v / 4.0;
+                s2 += (v / 4.0) * (v / 4.0);
+            }
+        for (double x : h) s2 += x * x;
+        pb->alpha = alpha;
+        pb->sigma_c = std::sqrt(s2);
+    }
+
+    pb->dim = 1ull << n;
+    const size_t dbytes = (size_t)pb->dim * diag_bytes_of(pb->diag_type);
+    if (qq_status st = check_device_fits(device, dbytes, "the cost diagonal"); st != QQ_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(device));
+    const int np = (int)pb->pair_b.size();
+    if (hipMalloc(&pb->d_diag, dbytes) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) for the diagonal failed", dbytes);
+    QQ_HIP(hipMalloc((void **)&pb->d_ell, sizeof(double) * n));
+    QQ_HIP(hipMalloc((void **)&pb->d_ell_i, sizeof(int32_t) * n));
+    QQ_HIP(hipMalloc((void **)&pb->d_pair_ij, sizeof(int32_t) * std::max(2, 2 * np)));
+    QQ_HIP(hipMalloc((void **)&pb->d_pair_b, sizeof(double) * std::max(1, np)));
+    QQ_HIP(hipMalloc((void **)&pb->d_pair_bi, sizeof(int32_t) * std::max(1, np)));
+    QQ_HIP(hipMemcpyAsync(pb->d_ell, pb->ell.data(), sizeof(double) * n, hipMemcpyHostToDevice, stream));
+    QQ_HIP(hipMemcpyAsync(pb->d_ell_i, pb->ell_i.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+    if (np) {
+        QQ_HIP(hipMemcpyAsync(pb->d_pair_ij, pb->pair_ij.data(), sizeof(int32_t) * 2 * np, hipMemcpyHostToDevice, stream));
+        QQ_HIP(hipMemcpyAsync(pb->d_pair_b, pb->pair_b.data(), sizeof(double) * np, hipMemcpyHostToDevice, stream));
+        QQ_HIP(hipMemcpyAsync(pb->d_pair_bi, pb->pair_bi.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, stream));
+    }
+    QQ_HIP(launch_cost_diag(n, pb->diag_type, pb->d_ell, pb->d_ell_i, np, pb->d_pair_ij, pb->d_pair_b, pb->d_pair_bi, c0,
+                            pb->c0_i, pb->d_diag, pb->dim, stream));
+
+    // min / argmin / max of C
+    const int nblk = (int)std::min<uint64_t>(1024, (pb->dim + 255) / 256);
+    DevBuf part;
+    QQ_HIP(hipMalloc(&part.p, (size_t)nblk * (2 * sizeof(double) + sizeof(uint64_t))));
+    double *d_part = static_cast<double *>(part.p);
+    uint64_t *d_idx = reinterpret_cast<uint64_t *>(d_part + 2 * nblk);
+    QQ_HIP(launch_minmax(pb->d_diag, pb->diag_type, pb->dim, d_part, d_idx, nblk, stream));
+    std::vector<double> hp(2 * nblk);
+    std::vector<uint64_t> hi(nblk);
+    QQ_HIP(hipMemcpyAsync(hp.data(), d_part, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipMemcpyAsync(hi.data(), d_idx, sizeof(uint64_t) * nblk, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    double mn = INFINITY, mx = -INFINITY;
+    uint64_t mi = ~0ull;
+    for (int k = 0; k < nblk; ++k) {
+        if (hp[2 * k] < mn || (hp[2 * k] == mn && hi[k] < mi)) {
+            mn = hp[2 * k];
+            mi = hi[k];
+        }
+        mx = std::max(mx, hp[2 * k + 1]);
+    }
+    pb->cmin = mn;
+    pb->cmax = mx;
+    pb->argmin = mi;
+    *out = guard.release();
+    return QQ_OK;
+}
+
+qq_status qq_problem_destroy(qq_problem *prob)
+{
+    delete prob;
+    return QQ_OK;
+}
+
+qq_status qq_problem_info(const qq_problem *pb, qq_info *out)
+{
+    if (!pb || !out) return fail(QQ_E_INVALID, "NULL argument");
+    qq_info in;
+    std::memset(&in, 0, sizeof in);
+    in.n = pb->n;
+    in.is_integer = pb->is_integer;
+    in.diag_bytes = diag_bytes_of(pb->diag_type);
+    in.num_qpus = pb->num_qpus;
+    in.c0 = pb->c0;
+    in.alpha = pb->alpha;
+    in.sigma_c = pb->sigma_c;
+    in.cmin = pb->cmin;
+    in.cmax = pb->cmax;
+    in.argmin_index = pb->argmin;
+    in.nonzero_couplings = (int64_t)pb->pair_b.size();
+    in.cross_terms = pb->cross_terms;
+    *out = in;
+    return QQ_OK;
+}
+
+qq_status qq_coefficients(const qq_problem *pb, double *ell, double *b, double *alpha, double *h, double *J)
+{
+    if (!pb) return fail(QQ_E_INVALID, "problem is NULL");
+    const int n = pb->n;
+    if (ell) std::copy(pb->ell.begin(), pb->ell.end(), ell);
+    if (b) std::copy(pb->b.begin(), pb->b.end(), b);
+    if (alpha) *alpha = pb->alpha;
+    if (h || J) {
+        std::vector<double> hh(n, 0.0), JJ((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i) hh[i] = -pb->ell[i] / 2.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                const double v = pb->b[(size_t)i * n + j];
+                hh[i] -= v / 4.0;
+                hh[j] -= v / 4.0;
+                JJ[(size_t)i * n + j] = v / 4.0;
+            }
+        if (h) std::copy(hh.begin(), hh.end(), h);
+        if (J) std::copy(JJ.begin(), JJ.end(), J);
+    }
+    return QQ_OK;
+}
+
+qq_status qq_cost_diagonal(const qq_problem *pb, void *out, int flags, void *stream_)
+{
+    if (!pb || !out) return fail(QQ_E_INVALID, "NULL argument");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(pb->device));
+    const size_t ob = (size_t)pb->dim * (pb->is_integer ? 4 : 8);
+    if (flags & QQ_OUT_ON_DEVICE) {
+        QQ_HIP(launch_widen_diag(pb->d_diag, pb->diag_type, pb->dim, out, stream));
+        return QQ_OK;
+    }
+    DevBuf tmp;
+    if (hipMalloc(&tmp.p, ob) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) failed", ob);
+    QQ_HIP(launch_widen_diag(pb->d_diag, pb->diag_type, pb->dim, tmp.p, stream));
+    QQ_HIP(hipMemcpyAsync(out, tmp.p, ob, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    return QQ_OK;
+}
+
+qq_status qq_set_allocation(qq_problem *pb, int M, const int32_t *qpu_of_var, const int32_t *capacities,
+                            int64_t *cross_out, int64_t *remote_out)
+{
+    if (!pb || !qpu_of_var) return fail(QQ_E_INVALID, "NULL argument");
+    const int n = pb->n;
+    if (M < 1 || M > QQ_MAX_QPUS) return fail(QQ_E_INVALID, "num_qpus = %d outside [1, %d]", M, QQ_MAX_QPUS);
+    std::vector<int> count(M, 0);
+    for (int i = 0; i < n; ++i) {
+        if (qpu_of_var[i] < 0 || qpu_of_var[i] >= M)
+            return fail(QQ_E_ALLOCATION, "variable %d assigned to QPU %d outside [0, %d)", i + 1, qpu_of_var[i], M);
+        ++count[qpu_of_var[i]];
+    }
+    for (int m = 0; m < M; ++m) {
+        if (count[m] == 0) return fail(QQ_E_ALLOCATION, "QPU %d has no variable (every QPU must be used)", m);
+        if (capacities && capacities[m] < 0) return fail(QQ_E_INVALID, "capacity of QPU %d is negative", m);
+        if (capacities && count[m] > capacities[m])
+            return fail(QQ_E_ALLOCATION, "QPU %d holds %d variables, capacity %d", m, count[m], capacities[m]);
+    }
+    int64_t cross = 0;
+    std::vector<int32_t> xij;
+    std::vector<double> xb;
+    std::vector<int32_t> xbi;
+    for (size_t k = 0; k < pb->pair_b.size(); ++k) {
+        const int i = pb->pair_ij[2 * k], j = pb->pair_ij[2 * k + 1];
+        if (qpu_of_var[i] != qpu_of_var[j]) {
+            ++cross;
+            xij.push_back(i);
+            xij.push_back(j);
+            xb.push_back(pb->pair_b[k]);
+            xbi.push_back(pb->pair_bi[k]);
+        }
+    }
+    PartDesc pd;
+    std::memset(&pd, 0, sizeof pd);
+    pd.nparts = M;
+    uint64_t total = 0;
+    for (int m = 0; m < M; ++m) {
+        pd.table_off[m] = total;
+        for (int i = 0; i < n; ++i)
+            if (qpu_of_var[i] == m) pd.vars[m][pd.nvars[m]++] = (uint8_t)i;
+        total += 1ull << pd.nvars[m];
+    }
+    const int es = diag_bytes_of(pb->diag_type);
+    if (qq_status st = check_device_fits(pb->device, (size_t)pb->dim * es * 2, "the cross-QPU diagonal"); st != QQ_OK)
+        return st;
+    QQ_HIP(hipSetDevice(pb->device));
+    // release a previous allocation
+    void *olds[] = {pb->d_qpu, pb->d_tables, pb->d_cross, pb->d_part};
+    for (void *q : olds)
+        if (q) QQ_HIP(hipFree(q));
+    pb->d_qpu = nullptr;
+    pb->d_tables = pb->d_cross = nullptr;
+    pb->d_part = nullptr;
+    pb->num_qpus = 0;
+    hipStream_t stream = nullptr;
+    QQ_HIP(hipMalloc((void **)&pb->d_qpu, sizeof(int32_t) * n));
+    QQ_HIP(hipMalloc(&pb->d_tables, total * es));
+    if (hipMalloc(&pb->d_cross, (size_t)pb->dim * es) != hipSuccess)
+        return fail(QQ_E_NOMEM, "hipMalloc for the cross diagonal failed");
+    QQ_HIP(hipMalloc((void **)&pb->d_part, sizeof(PartDesc)));
+    QQ_HIP(hipMemcpy(pb->d_qpu, qpu_of_var, sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    QQ_HIP(hipMemcpy(pb->d_part, &pd, sizeof(PartDesc), hipMemcpyHostToDevice));
+    QQ_HIP(launch_local_tables(n, pb->diag_type, pb->d_part, pb->d_ell, pb->d_ell_i, (int)pb->pair_b.size(),
+                               pb->d_pair_ij, pb->d_pair_b, pb->d_pair_bi, pb->d_qpu, pb->c0, pb->c0_i, pb->d_tables,
+                               total, stream));
+    // cross diagonal: the cost diagonal of the cross couplings alone (no linear terms, no constant)
+    {
+        const int nx = (int)xb.size();
+        DevBuf zero_ell, zero_elli, dij, db, dbi;
+        QQ_HIP(hipMalloc(&zero_ell.p, sizeof(double) * n));
+        QQ_HIP(hipMalloc(&zero_elli.p, sizeof(int32_t) * n));
+        QQ_HIP(hipMemset(zero_ell.p, 0, sizeof(double) * n));
+        QQ_HIP(hipMemset(zero_elli.p, 0, sizeof(int32_t) * n));
+        QQ_HIP(hipMalloc(&dij.p, sizeof(int32_t) * std::max(2, 2 * nx)));
+        QQ_HIP(hipMalloc(&db.p, sizeof(double) * std::max(1, nx)));
+        QQ_HIP(hipMalloc(&dbi.p, sizeof(int32_t) * std::max(1, nx)));
+        if (nx) {
+            QQ_HIP(hipMemcpy(dij.p, xij.data(), sizeof(int32_t) * 2 * nx, hipMemcpyHostToDevice));
+            QQ_HIP(hipMemcpy(db.p, xb.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
+            QQ_HIP(hipMemcpy(dbi.p, xbi.data(), sizeof(int32_t) * nx, hipMemcpyHostToDevice));
+        }
+        QQ_HIP(launch_cost_diag(n, pb->diag_type, static_cast<double *>(zero_ell.p), static_cast<int32_t *>(zero_elli.p),
+                                nx, static_cast<int32_t *>(dij.p), static_cast<double *>(db.p),
+                                static_cast<int32_t *>(dbi.p), 0.0, 0, pb->d_cross, pb->dim, stream));
+        QQ_HIP(hipDeviceSynchronize());
+    }
+    pb->num_qpus = M;
+    pb->qpu.assign(qpu_of_var, qpu_of_var + n);
+    pb->cross_terms = cross;
+    if (cross_out) *cross_out = cross;
+    if (remote_out) *remote_out = 2 * cross;
+    return QQ_OK;
+}
+
+qq_status qq_workspace_size(const qq_problem *pb, int p, int batch, int flags, size_t *bytes)
+{
+    if (!bytes) return fail(QQ_E_INVALID, "bytes is NULL");
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    const Plan plan = make_plan(pb->n, p, plan_mode(flags, false));
+    *bytes = make_layout(pb, p, batch, flags, plan).total;
+    return QQ_OK;
+}
+
+qq_status qq_evaluate(qq_problem *pb, int p, int batch, const double *params, int flags, void *workspace,
+                      size_t ws_bytes, void *stream_, double *energy_out, double *grad_out)
+{
+    g_err.clear();
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    if (!params) return fail(QQ_E_INVALID, "params is NULL");
+    if (!energy_out) return fail(QQ_E_INVALID, "energy_out is NULL");
+    if ((flags & QQ_GRAD) && !grad_out) return fail(QQ_E_INVALID, "QQ_GRAD requires grad_out");
+    if (!(flags & QQ_PARAMS_ON_DEVICE))
+        if (qq_status st = check_params_host(params, (size_t)batch * 2 * p); st != QQ_OK) return st;
+    const Plan plan = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false));
+    const Layout L = make_layout(pb, p, batch, flags, plan);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(pb->device));
+    DevBuf own;
+    char *ws = static_cast<char *>(workspace);
+    if (!ws) {
+        if (qq_status st = check_device_fits(pb->device, L.total, "the workspace"); st != QQ_OK) return st;
+        if (hipMalloc(&own.p, L.total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) for the workspace failed", L.total);
+        ws = static_cast<char *>(own.p);
+    } else if (ws_bytes < L.total) {
+        return fail(QQ_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
+    }
+    if (qq_status st = eval_core(pb, p, batch, params, flags, plan, L, ws, stream); st != QQ_OK) return st;
+    const double *d_out = reinterpret_cast<const double *>(ws + L.out);
+    const size_t nout = 1 + 2 * (size_t)p;
+    const bool grad = flags & QQ_GRAD;
+    if (flags & QQ_OUT_ON_DEVICE) {
+        QQ_HIP(hipMemcpy2DAsync(energy_out, sizeof(double), d_out, nout * sizeof(double), sizeof(double), batch,
+                                hipMemcpyDeviceToDevice, stream));
+        if (grad)
+            QQ_HIP(hipMemcpy2DAsync(grad_out, 2 * p * sizeof(double), d_out + 1, nout * sizeof(double),
+                                    2 * p * sizeof(double), batch, hipMemcpyDeviceToDevice, stream));
+        if (own.p) QQ_HIP(hipStreamSynchronize(stream));
+        return QQ_OK;
+    }
+    std::vector<double> h((size_t)batch * nout);
+    QQ_HIP(hipMemcpyAsync(h.data(), d_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    for (int b = 0; b < batch; ++b) {
+        energy_out[b] = h[(size_t)b * nout];
+        if (grad)
+            for (int j = 0; j < 2 * p; ++j) grad_out[(size_t)b * 2 * p + j] = h[(size_t)b * nout + 1 + j];
+    }
+    return QQ_OK;
+}
+
+// Forward evaluation of one parameter set with the final state kept in `own`.
+static qq_status state_into(qq_problem *pb, int p, const double *params, int flags, hipStream_t stream, DevBuf &own,
+                            Layout &L)
+{
+    if (qq_status st = validate_eval(pb, p, 1, flags); st != QQ_OK) return st;
+    if (!params) return fail(QQ_E_INVALID, "params is NULL");
+    if (!(flags & QQ_PARAMS_ON_DEVICE))
+        if (qq_status st = check_params_host(params, 2 * (size_t)p); st != QQ_OK) return st;
+    const int f = flags & ~QQ_GRAD;
+    const Plan plan = make_plan(pb->n, p, plan_mode(f, true));
+    L = make_layout(pb, p, 1, f, plan);
+    QQ_HIP(hipSetDevice(pb->device));
+    if (qq_status st = check_device_fits(pb->device, L.total, "the state"); st != QQ_OK) return st;
+    if (hipMalloc(&own.p, L.total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) failed", L.total);
+    return eval_core(pb, p, 1, params, f, plan, L, static_cast<char *>(own.p), stream);
+}
+
+qq_status qq_state(qq_problem *pb, int p, const double *params, int flags, void *psi_out, void *stream_)
+{
+    g_err.clear();
+    if (!psi_out) return fail(QQ_E_INVALID, "psi_out is NULL");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DevBuf own;
+    Layout L;
+    if (qq_status st = state_into(pb, p, params, flags, stream, own, L); st != QQ_OK) return st;
+    const size_t bytes = (size_t)pb->dim * ((flags & QQ_C128) ? 16 : 8);
+    QQ_HIP(hipMemcpyAsync(psi_out, static_cast<char *>(own.p) + L.psi, bytes,
+                          (flags & QQ_OUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    return QQ_OK;
+}
+
+qq_status qq_probabilities(qq_problem *pb, int p, const double *params, int flags, double *prob_out, void *stream_)
+{
+    g_err.clear();
+    if (!prob_out) return fail(QQ_E_INVALID, "prob_out is NULL");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DevBuf own;
+    Layout L;
+    if (qq_status st = state_into(pb, p, params, flags, stream, own, L); st != QQ_OK) return st;
+    const void *psi = static_cast<char *>(own.p) + L.psi;
+    if (flags & QQ_OUT_ON_DEVICE) {
+        QQ_HIP(launch_probabilities(psi, flags & QQ_C128, pb->dim, prob_out, stream));
+        QQ_HIP(hipStreamSynchronize(stream));
+        return QQ_OK;
+    }
+    DevBuf tmp;
+    if (hipMalloc(&tmp.p, (size_t)pb->dim * sizeof(double)) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc failed");
+    QQ_HIP(launch_probabilities(psi, flags & QQ_C128, pb->dim, static_cast<double *>(tmp.p), stream));
+    QQ_HIP(hipMemcpyAsync(prob_out, tmp.p, (size_t)pb->dim * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    return QQ_OK;
+}
+
+qq_status qq_topk(qq_problem *pb, int p, const double *params, int flags, int k, uint64_t *idx_out, double *prob_out,
+                  double *cost_out, void *stream_)
+{
+    g_err.clear();
+    if (k < 1 || k > QQ_MAX_TOPK) return fail(QQ_E_INVALID, "k = %d outside [1, %d]", k, QQ_MAX_TOPK);
+    if (pb && (uint64_t)k > pb->dim) return fail(QQ_E_INVALID, "k = %d exceeds 2^n", k);
+    if (!idx_out || !prob_out) return fail(QQ_E_INVALID, "idx_out / prob_out is NULL");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DevBuf own;
+    Layout L;
+    if (qq_status st = state_into(pb, p, params, flags, stream, own, L); st != QQ_OK) return st;
+    const void *psi = static_cast<char *>(own.p) + L.psi;
+    const int nblocks = (int)std::min<uint64_t>(1024, (pb->dim + 255) / 256);
+    DevBuf scratch;
+    const size_t sb = (size_t)nblocks * k * 16 + (size_t)k * 24 + 256;
+    if (hipMalloc(&scratch.p, sb) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc failed");
+    char *sc = static_cast<char *>(scratch.p);
+    uint64_t *d_idx = reinterpret_cast<uint64_t *>(sc + (size_t)nblocks * k * 16);
+    double *d_prob = reinterpret_cast<double *>(d_idx + k);
+    double *d_cost = d_prob + k;
+    QQ_HIP(launch_topk(psi, flags & QQ_C128, pb->dim, k, pb->d_diag, pb->diag_type, d_idx, d_prob, d_cost, sc, nblocks,
+                       stream));
+    std::vector<uint64_t> hi(k);
+    std::vector<double> hp(k), hc(k);
+    QQ_HIP(hipMemcpyAsync(hi.data(), d_idx, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipMemcpyAsync(hp.data(), d_prob, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipMemcpyAsync(hc.data(), d_cost, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    std::copy(hi.begin(), hi.end(), idx_out);
+    std::copy(hp.begin(), hp.end(), prob_out);
+    if (cost_out) std::copy(hc.begin(), hc.end(), cost_out);
+    return QQ_OK;
+}
+
+qq_status qq_evaluate_plain(qq_problem *pb, int p, const double *params, int flags, void *stream_, double *energy_out,
+                            double *grad_out)
+{
+    g_err.clear();
+    if (qq_status st = validate_eval(pb, p, 1, flags); st != QQ_OK) return st;
+    if (flags & (QQ_PARTITIONED | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE))
+        return fail(QQ_E_UNSUPPORTED, "the plain per-gate path takes host params/outputs and no partitioning");
+    if (!params || !energy_out) return fail(QQ_E_INVALID, "NULL argument");
+    if ((flags & QQ_GRAD) && !grad_out) return fail(QQ_E_INVALID, "QQ_GRAD requires grad_out");
+    if (qq_status st = check_params_host(params, 2 * (size_t)p); st != QQ_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const bool grad = flags & QQ_GRAD;
+    const size_t state = (size_t)pb->dim * 16;
+    const int nblocks = (int)std::min<uint64_t>(2048, std::max<uint64_t>(1, pb->dim / 512));
+    const size_t total = align_up(state) * (grad ? 2 : 1) + align_up(sizeof(double) * nblocks) +
+                         align_up(sizeof(double) * (1 + 2 * p));
+    QQ_HIP(hipSetDevice(pb->device));
+    if (qq_status st = check_device_fits(pb->device, total, "the plain-path states"); st != QQ_OK) return st;
+    DevBuf own;
+    if (hipMalloc(&own.p, total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) failed", total);
+    char *ws = static_cast<char *>(own.p);
+    PlainArgs a;
+    a.n = pb->n;
+    a.p = p;
+    a.grad = grad;
+    a.dim = pb->dim;
+    a.params = params;
+    a.diag = pb->d_diag;
+    a.diag_type = pb->diag_type;
+    a.psi = ws;
+    a.lam = grad ? ws + align_up(state) : nullptr;
+    a.partial = reinterpret_cast<double *>(ws + align_up(state) * (grad ? 2 : 1));
+    a.result = reinterpret_cast<double *>(ws + align_up(state) * (grad ? 2 : 1) + align_up(sizeof(double) * nblocks));
+    a.nblocks = nblocks;
+    QQ_HIP(run_plain(a, stream));
+    std::vector<double> h(1 + 2 * p);
+    QQ_HIP(hipMemcpyAsync(h.data(), a.result, sizeof(double) * h.size(), hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    energy_out[0] = h[0];
+    if (grad)
+        for (int j = 0; j < 2 * p; ++j) grad_out[j] = h[1 + j];
+    return QQ_OK;
+}
+
+}  // extern "C"

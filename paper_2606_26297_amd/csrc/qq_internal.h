@@ -1,0 +1,148 @@
+// qq_internal.h -- internal types shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/qaoa_qubo.h"
+
+namespace qq {
+
+// ---- tile geometry of the fused pass kernel ------------------------------------------------
+// A tile is 2^12 amplitudes of one state held in registers by 256 threads
+// (4 waves), 16 amplitudes per thread and state.  Tile-local bit j maps to a
+// global qubit: bits 0..3 always map to qubits 0..3 (a 16-amplitude, 128-byte
+// contiguous run for complex64); bits 4..11 map either to qubits 4..11 (the
+// "low" tile, fully contiguous) or to qubits pos4..pos4+7 (a "high" tile).
+// The 12 tile bits form three 4-bit register groups; a group is mixed in
+// registers after an LDS transpose brings it into the per-thread register index.
+constexpr int kTileBits = 12;
+constexpr int kTile = 1 << kTileBits;
+constexpr int kThreads = 256;
+constexpr int kRegs = 16;
+constexpr int kMaxOps = 4 * QQ_MAX_P + 4;
+constexpr int kMaxLocalSlots = 4;
+constexpr int kMaxSlots = 512;
+constexpr int kMaxImmSlots = 1 + 2 * QQ_MAX_P;  // slots of a single-pass plan
+constexpr uint8_t kNoSlot = 0xff;
+
+enum OpKind : uint8_t {
+    OP_MIX = 1,            // RX(+-2 beta_k) on the active tile bits of the selected states
+    OP_PHASE = 2,          // states *= exp(-+ i gamma_k C)
+    OP_ENERGY = 3,         // acc += |psi|^2 C
+    OP_ENERGY_LAMBDA = 4,  // acc += |psi|^2 C ; lambda = C psi (lambda becomes live)
+    OP_GGAMMA = 5          // acc += C Im(conj(lambda) psi) ; optionally un-phase both states
+};
+
+enum OpFlag : uint8_t {
+    OPF_INVERSE = 1,      // MIX/PHASE: apply the inverse rotation
+    OPF_UNPHASE = 2,      // GGAMMA: afterwards multiply both states by exp(+i gamma_k C)
+    OPF_PARTITIONED = 4   // PHASE / GGAMMA un-phase: per-QPU local factors then the cross factor
+};
+
+struct Op {
+    uint8_t kind;
+    uint8_t layer;   // 0-based layer k
+    uint8_t states;  // bit 0: psi, bit 1: lambda
+    uint8_t flags;   // OpFlag
+    uint16_t active; // MIX: tile-bit mask
+    uint8_t slot;    // local accumulator slot, kNoSlot = none
+    uint8_t pad;
+};
+
+enum PassFlag : uint32_t {
+    PF_INIT = 1,       // psi = 2^(-n/2) everywhere (no load)
+    PF_LOAD_PSI = 2,
+    PF_LOAD_LAM = 4,
+    PF_STORE_PSI = 8,
+    PF_STORE_LAM = 16
+};
+
+enum DiagType : int { DIAG_F64 = 0, DIAG_I32 = 1, DIAG_I16 = 2 };
+
+// Variables of each QPU for the partitioned phase: local table m is indexed by
+// the bits of its variables, in ascending variable order.
+struct PartDesc {
+    int nparts;
+    int nvars[QQ_MAX_QPUS];
+    uint64_t table_off[QQ_MAX_QPUS];  // element offset of table m inside the packed tables buffer
+    uint8_t vars[QQ_MAX_QPUS][QQ_MAX_N];
+};
+
+struct PassArgs {
+    int n;
+    int p;
+    int B;            // states in this launch
+    int G;            // workgroups per state
+    uint64_t tiles;   // tiles per state
+    uint64_t dim_mask;
+    int pos4, pos8;   // global positions of tile bits 4 and 8
+    int high;         // 0: tile bits are qubits 0..11, 1: qubits 0..3 and pos4..pos4+7
+    int hshift;       // high tile: number of tile-index bits placed at qubits 4..pos4-1
+    uint32_t flags;
+    int nops;
+    int nslots;
+    int slot_base;
+    int slot_stride;  // B * G
+    double amp0;
+    const double *params;  // device [B][2p]
+    const void *diag;
+    void *psi;
+    void *lam;
+    uint64_t state_stride;
+    double *partial;
+    const void *part_tables;  // packed local tables (diag element type)
+    const void *cross_diag;   // 2^n cross diagonal (diag element type)
+    const PartDesc *part;     // device
+    Op ops[kMaxOps];
+};
+
+struct FinalizeArgs {
+    int B;
+    int G;
+    int p;
+    int nslots;
+    double escale;        // 2^(n-12) for replicated small states, else 1
+    const double *partial;
+    double *out;          // [B][1 + 2p] : energy, then interleaved gradient
+    uint16_t slot_out[kMaxSlots];  // output index of each global slot
+};
+
+// Kernel launchers (qq_kernels.hip).
+hipError_t launch_pass(const PassArgs &a, bool c128, int nstates, int diag_type, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+hipError_t launch_cost_diag(int n, int diag_type, const double *d_ell, const int32_t *d_ell_i, int npairs,
+                            const int32_t *d_pair_ij, const double *d_pair_b, const int32_t *d_pair_bi, double c0,
+                            int32_t c0_i, void *d_out, uint64_t dim, hipStream_t s);
+hipError_t launch_minmax(const void *d_diag, int diag_type, uint64_t dim, double *d_part, uint64_t *d_idx,
+                         int nblocks, hipStream_t s);
+hipError_t launch_widen_diag(const void *d_diag, int diag_type, uint64_t dim, void *d_out, hipStream_t s);
+hipError_t launch_probabilities(const void *psi, bool c128, uint64_t dim, double *out, hipStream_t s);
+hipError_t launch_topk(const void *psi, bool c128, uint64_t dim, int k, const void *diag, int diag_type,
+                       uint64_t *d_idx, double *d_prob, double *d_cost, void *scratch, int nblocks,
+                       hipStream_t s);
+hipError_t launch_local_tables(int n, int diag_type, const PartDesc *d_pd, const double *d_ell,
+                               const int32_t *d_ell_i, int npairs, const int32_t *d_pair_ij, const double *d_pair_b,
+                               const int32_t *d_pair_bi, const int32_t *d_qpu, double c0, int32_t c0_i, void *d_tables,
+                               uint64_t total, hipStream_t s);
+
+// Plain complex128 per-gate path (qq_plain.hip).
+struct PlainArgs {
+    int n;
+    int p;
+    int grad;
+    uint64_t dim;
+    const double *params;  // host [2p]
+    const void *diag;
+    int diag_type;
+    void *psi;   // device complex128 [dim]
+    void *lam;   // device complex128 [dim] (grad only)
+    double *partial;  // device scratch [nblocks]
+    double *result;   // device scratch [1 + 2p]
+    int nblocks;
+};
+hipError_t run_plain(const PlainArgs &a, hipStream_t s);
+
+}  // namespace qq

@@ -1,0 +1,856 @@
+// qq_kernels.hip -- gfx950 kernels of the exact QAOA-for-QUBO statevector engine.
+//
+// The method (cost unitary eq. (10), mixer eq. (12)-(13), state eq. (11),
+// objective eq. (15)/(17)) is executed as a sequence of "passes".  A pass
+// streams every amplitude of the state(s) once through registers in tiles of
+// 2^12 amplitudes and applies, in registers, a short program of operations:
+//   MIX      RX(+-2 beta_k) on a subset of the tile's qubits (butterflies on
+//            register-resident bits; LDS transposes rotate which 4 tile bits
+//            are register bits),
+//   PHASE    multiplication by exp(-+ i gamma_k C(z)) (FP64 argument, FP64
+//            reduction modulo 2 pi, then the rotation in the state precision),
+//   ENERGY   FP64 accumulation of |psi|^2 C,
+//   ENERGY_LAMBDA / GGAMMA   the seeds and gamma-derivatives of the adjoint sweep.
+// The beta-derivative sum_q Im<lambda|X_q|psi> is accumulated inside the
+// MIX butterflies of the backward sweep.  All accumulations are FP64 and are
+// reduced in a fixed order (no floating-point atomics), so results are
+// bit-reproducible.
+#include "qq_internal.h"
+#include "qq_twopi.h"
+
+namespace qq {
+namespace {
+
+template <typename R>
+struct Cx;
+template <>
+struct Cx<float> {
+    using T = float2;
+};
+template <>
+struct Cx<double> {
+    using T = double2;
+};
+
+template <typename C2, typename R>
+__device__ __forceinline__ C2 mk(R x, R y)
+{
+    C2 v;
+    v.x = x;
+    v.y = y;
+    return v;
+}
+
+// Bank-conflict-avoiding LDS address of tile-local amplitude i (a bijection on [0, 4096)).
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 15) ^ (((i >> 8) & 1) << 4); }
+
+// Tile-local index held by thread t in register r under layout L:
+//   L = 2: register bits are tile bits 8..11, thread bits are tile bits 0..7
+//   L = 1: register bits are tile bits 4..7,  thread bits are tile bits 0..3, 8..11
+//   L = 0: register bits are tile bits 0..3,  thread bits are tile bits 4..11
+template <int L>
+__device__ __forceinline__ int lidx(int t, int r)
+{
+    if constexpr (L == 2) return t + 256 * r;
+    else if constexpr (L == 1) return (t & 15) + 16 * r + ((t >> 4) << 8);
+    else return r + 16 * t;
+}
+
+template <typename DT>
+__device__ __forceinline__ double ldc(const void *p, uint64_t i)
+{
+    return (double)(static_cast<const DT *>(p)[i]);
+}
+
+// theta mod 2 pi in [-pi, pi]: k = rint(theta / 2pi), r = (theta - k HI) - k LO with FMAs
+// (Cody-Waite reduction with a double-double 2 pi).
+__device__ __forceinline__ double reduce_2pi(double th)
+{
+    const double k = rint(th * QQ_INV_TWO_PI);
+    const double r = fma(-k, QQ_TWO_PI_HI, th);
+    return fma(-k, QQ_TWO_PI_LO, r);
+}
+
+__device__ __forceinline__ void phase_cs(double theta, float &c, float &s)
+{
+    const float r = (float)reduce_2pi(theta);
+    sincosf(r, &s, &c);
+}
+__device__ __forceinline__ void phase_cs(double theta, double &c, double &s)
+{
+    sincos(reduce_2pi(theta), &s, &c);
+}
+
+// ---- LDS transposes -----------------------------------------------------------------------
+// complex64: one round of float2 words; complex128: two rounds of doubles (x, then y),
+// so both fit a 32 KiB buffer.
+template <int L, typename C2>
+__device__ __forceinline__ void lds_put(float2 *lds, const C2 (&v)[kRegs], int t, int)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) lds[swz(lidx<L>(t, r))] = v[r];
+}
+template <int L, typename C2>
+__device__ __forceinline__ void lds_get(const float2 *lds, C2 (&v)[kRegs], int t, int)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) v[r] = lds[swz(lidx<L>(t, r))];
+}
+template <int L>
+__device__ __forceinline__ void lds_put(double *lds, const double2 (&v)[kRegs], int t, int comp)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) lds[swz(lidx<L>(t, r))] = comp ? v[r].y : v[r].x;
+}
+template <int L>
+__device__ __forceinline__ void lds_get(const double *lds, double2 (&v)[kRegs], int t, int comp)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        const double w = lds[swz(lidx<L>(t, r))];
+        if (comp) v[r].y = w;
+        else v[r].x = w;
+    }
+}
+
+template <typename W, typename C2>
+__device__ __forceinline__ void transpose1(W *lds, C2 (&v)[kRegs], int t, int from, int to)
+{
+    constexpr int rounds = sizeof(C2) / sizeof(W);
+#pragma unroll
+    for (int c = 0; c < rounds; ++c) {
+        __syncthreads();
+        if (from == 0) lds_put<0>(lds, v, t, c);
+        else if (from == 1) lds_put<1>(lds, v, t, c);
+        else lds_put<2>(lds, v, t, c);
+        __syncthreads();
+        if (to == 0) lds_get<0>(lds, v, t, c);
+        else if (to == 1) lds_get<1>(lds, v, t, c);
+        else lds_get<2>(lds, v, t, c);
+    }
+}
+
+// ---- butterflies --------------------------------------------------------------------------
+// RX(2 beta) on tile bit K of the register group: (a, b) -> (c a - i s b, -i s a + c b).
+template <int K, typename C2, typename R>
+__device__ __forceinline__ void rx_bit(C2 (&v)[kRegs], R c, R s)
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        if (r & (1 << K)) continue;
+        const C2 a = v[r], b = v[r | (1 << K)];
+        v[r] = mk<C2, R>(c * a.x + s * b.y, c * a.y - s * b.x);
+        v[r | (1 << K)] = mk<C2, R>(c * b.x + s * a.y, c * b.y - s * a.x);
+    }
+}
+
+// sum over pairs of bit K of Im(conj(l0) a1 + conj(l1) a0), FP64 (products of FP32 inputs are exact).
+template <int K, typename C2>
+__device__ __forceinline__ double xexp_bit(const C2 (&a)[kRegs], const C2 (&l)[kRegs])
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        if (r & (1 << K)) continue;
+        const int q = r | (1 << K);
+        acc = fma((double)l[r].x, (double)a[q].y, acc);
+        acc = fma(-(double)l[r].y, (double)a[q].x, acc);
+        acc = fma((double)l[q].x, (double)a[r].y, acc);
+        acc = fma(-(double)l[q].y, (double)a[r].x, acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void add_slot(double (&acc)[kMaxLocalSlots], int slot, double v)
+{
+    switch (slot) {
+    case 0: acc[0] += v; break;
+    case 1: acc[1] += v; break;
+    case 2: acc[2] += v; break;
+    case 3: acc[3] += v; break;
+    default: break;
+    }
+}
+
+// Index of the local table entry of a QPU: the bits of its variables, in ascending order.
+__device__ __forceinline__ uint64_t compress_bits(uint64_t z, const uint8_t *vars, int nv)
+{
+    uint64_t u = 0;
+    for (int j = 0; j < nv; ++j) u |= ((z >> vars[j]) & 1ull) << j;
+    return u;
+}
+
+template <typename R, typename C2>
+__device__ __forceinline__ void rot_phase(C2 &v, R c, R s)
+{
+    // v * (c - i s)
+    v = mk<C2, R>(v.x * c + v.y * s, v.y * c - v.x * s);
+}
+
+template <typename R, int NS, typename DT>
+__global__ void __launch_bounds__(kThreads) pass_kernel(const PassArgs a)
+{
+    using C2 = typename Cx<R>::T;
+    using W = typename std::conditional<sizeof(R) == 4, float2, double>::type;
+    __shared__ W lds[kTile];
+    __shared__ R s_cb[QQ_MAX_P], s_sb[QQ_MAX_P];
+    __shared__ double s_gam[QQ_MAX_P];
+    __shared__ double s_red[kThreads / 64][kMaxLocalSlots];
+    __shared__ double s_imm[kMaxImmSlots];
+    __shared__ double s_wsum[kThreads / 64];
+
+    const int t = threadIdx.x;
+    for (int k = t; k < kMaxImmSlots; k += kThreads) s_imm[k] = 0.0;
+    const int b = blockIdx.x % a.B;
+    const int g = blockIdx.x / a.B;
+    {
+        const double *x = a.params + (size_t)b * 2 * a.p;
+        if (t < a.p) {
+            double sb, cb;
+            sincos(x[2 * t + 1], &sb, &cb);
+            s_cb[t] = (R)cb;
+            s_sb[t] = (R)sb;
+            s_gam[t] = x[2 * t];
+        }
+    }
+    __syncthreads();
+
+    const uint64_t off2 = (uint64_t)(t & 15) | ((uint64_t)(t >> 4) << a.pos4);
+    const uint64_t st2 = 1ull << a.pos8;
+    const uint64_t off1 = (uint64_t)(t & 15) | ((uint64_t)(t >> 4) << a.pos8);
+    const uint64_t st1 = 1ull << a.pos4;
+
+    C2 *psi = static_cast<C2 *>(a.psi) + (size_t)b * a.state_stride;
+    C2 *lam = NS > 1 ? static_cast<C2 *>(a.lam) + (size_t)b * a.state_stride : nullptr;
+
+    C2 v[NS][kRegs];
+    double acc[kMaxLocalSlots] = {0.0, 0.0, 0.0, 0.0};
+
+    for (uint64_t tile = g; tile < a.tiles; tile += a.G) {
+        uint64_t base;
+        if (a.high) base = ((tile & ((1ull << a.hshift) - 1)) << 4) | ((tile >> a.hshift) << (a.pos4 + 8));
+        else base = tile << kTileBits;
+
+        int live = 0;
+        if (a.flags & PF_INIT) {
+#pragma unroll
+            for (int r = 0; r < kRegs; ++r) v[0][r] = mk<C2, R>((R)a.amp0, (R)0);
+            live |= 1;
+        }
+        if (a.flags & PF_LOAD_PSI) {
+#pragma unroll
+            for (int r = 0; r < kRegs; ++r) v[0][r] = psi[base + off2 + r * st2];
+            live |= 1;
+        }
+        if constexpr (NS > 1) {
+            if (a.flags & PF_LOAD_LAM) {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) v[1][r] = lam[base + off2 + r * st2];
+                live |= 2;
+            }
+        }
+        int cur = 2;
+
+        auto to_layout = [&](int to) {
+            if (to == cur) return;
+            if (live & 1) transpose1<W>(lds, v[0], t, cur, to);
+            if constexpr (NS > 1)
+                if (live & 2) transpose1<W>(lds, v[1], t, cur, to);
+            cur = to;
+        };
+        auto coalesced = [&]() {
+            if (cur == 0) to_layout(1);
+        };
+        // Slots 0..3 accumulate in registers across tiles; higher slots (only in
+        // single-pass plans) are reduced over the workgroup at once into LDS.
+        auto accumulate = [&](int slot, double val) {
+            if (slot < kMaxLocalSlots) {
+                add_slot(acc, slot, val);
+                return;
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) val += __shfl_xor(val, d, 64);
+            if ((t & 63) == 0) s_wsum[t >> 6] = val;
+            __syncthreads();
+            if (t == 0) s_imm[slot] += (s_wsum[0] + s_wsum[1]) + (s_wsum[2] + s_wsum[3]);
+            __syncthreads();
+        };
+
+        for (int o = 0; o < a.nops; ++o) {
+            const Op op = a.ops[o];
+            if (op.kind == OP_MIX) {
+                const R cb = s_cb[op.layer];
+                const R sb = (op.flags & OPF_INVERSE) ? -s_sb[op.layer] : s_sb[op.layer];
+                int seq[3], ns = 0;
+                const int need = (((op.active & 0x00f) != 0) << 0) | (((op.active & 0x0f0) != 0) << 1) |
+                                 (((op.active & 0xf00) != 0) << 2);
+                if (need & (1 << cur)) seq[ns++] = cur;
+                if ((need & 1) && cur != 0) seq[ns++] = 0;
+                if ((need & 2) && cur != 1) seq[ns++] = 1;
+                if ((need & 4) && cur != 2) seq[ns++] = 2;
+                for (int k = 0; k < ns; ++k) {
+                    const int gi = seq[k];
+                    to_layout(gi);
+                    const int m = (op.active >> (4 * gi)) & 15;
+                    double gacc = 0.0;
+#define QQ_BIT(K)                                                                   \
+    if (m & (1 << K)) {                                                             \
+        if constexpr (NS > 1)                                                       \
+            if (op.slot != kNoSlot) gacc += xexp_bit<K>(v[0], v[1]);                      \
+        if (op.states & 1) rx_bit<K>(v[0], cb, sb);                                 \
+        if constexpr (NS > 1)                                                       \
+            if (op.states & 2) rx_bit<K>(v[1], cb, sb);                             \
+    }
+                    QQ_BIT(0)
+                    QQ_BIT(1)
+                    QQ_BIT(2)
+                    QQ_BIT(3)
+#undef QQ_BIT
+                    if (op.slot != kNoSlot) accumulate(op.slot, gacc);
+                }
+            } else {
+                coalesced();
+                const uint64_t off = cur == 2 ? off2 : off1;
+                const uint64_t st = cur == 2 ? st2 : st1;
+                const double gam = s_gam[op.layer];
+                double tacc = 0.0;
+                if (op.kind == OP_PHASE) {
+                    const bool inv = op.flags & OPF_INVERSE;
+#pragma unroll
+                    for (int r = 0; r < kRegs; ++r) {
+                        const uint64_t gi = (base + off + r * st) & a.dim_mask;
+                        if (op.flags & OPF_PARTITIONED) {
+                            for (int m = 0; m < a.part->nparts + 1; ++m) {
+                                double cm;
+                                if (m < a.part->nparts)
+                                    cm = ldc<DT>(a.part_tables, a.part->table_off[m] +
+                                                                    compress_bits(gi, a.part->vars[m], a.part->nvars[m]));
+                                else cm = ldc<DT>(a.cross_diag, gi);
+                                R c, s;
+                                phase_cs(gam * cm, c, s);
+                                if (inv) s = -s;
+                                if (op.states & 1) rot_phase<R>(v[0][r], c, s);
+                                if constexpr (NS > 1)
+                                    if (op.states & 2) rot_phase<R>(v[1][r], c, s);
+                            }
+                        } else {
+                            R c, s;
+                            phase_cs(gam * ldc<DT>(a.diag, gi), c, s);
+                            if (inv) s = -s;
+                            if (op.states & 1) rot_phase<R>(v[0][r], c, s);
+                            if constexpr (NS > 1)
+                                if (op.states & 2) rot_phase<R>(v[1][r], c, s);
+                        }
+                    }
+                } else if (op.kind == OP_ENERGY || op.kind == OP_ENERGY_LAMBDA) {
+#pragma unroll
+                    for (int r = 0; r < kRegs; ++r) {
+                        const uint64_t gi = (base + off + r * st) & a.dim_mask;
+                        const double cz = ldc<DT>(a.diag, gi);
+                        const double re = (double)v[0][r].x, im = (double)v[0][r].y;
+                        tacc = fma(fma(re, re, im * im), cz, tacc);
+                        if constexpr (NS > 1)
+                            if (op.kind == OP_ENERGY_LAMBDA) v[1][r] = mk<C2, R>((R)(cz * re), (R)(cz * im));
+                    }
+                    if (op.kind == OP_ENERGY_LAMBDA) live |= 2;
+                } else if (op.kind == OP_GGAMMA) {
+                    if constexpr (NS > 1) {
+                        const bool unph = op.flags & OPF_UNPHASE;
+#pragma unroll
+                        for (int r = 0; r < kRegs; ++r) {
+                            const uint64_t gi = (base + off + r * st) & a.dim_mask;
+                            const double cz = ldc<DT>(a.diag, gi);
+                            const C2 ps = v[0][r], la = v[1][r];
+                            const double im = fma((double)la.x, (double)ps.y, -(double)la.y * (double)ps.x);
+                            tacc = fma(cz, im, tacc);
+                            if (unph) {
+                                if (op.flags & OPF_PARTITIONED) {
+                                    for (int m = 0; m < a.part->nparts + 1; ++m) {
+                                        double cm;
+                                        if (m < a.part->nparts)
+                                            cm = ldc<DT>(a.part_tables,
+                                                         a.part->table_off[m] +
+                                                             compress_bits(gi, a.part->vars[m], a.part->nvars[m]));
+                                        else cm = ldc<DT>(a.cross_diag, gi);
+                                        R c, s;
+                                        phase_cs(gam * cm, c, s);
+                                        rot_phase<R>(v[0][r], c, -s);
+                                        rot_phase<R>(v[1][r], c, -s);
+                                    }
+                                } else {
+                                    R c, s;
+                                    phase_cs(gam * cz, c, s);
+                                    rot_phase<R>(v[0][r], c, -s);
+                                    rot_phase<R>(v[1][r], c, -s);
+                                }
+                            }
+                        }
+                    }
+                }
+                if (op.slot != kNoSlot) accumulate(op.slot, tacc);
+            }
+        }
+
+        if (a.flags & (PF_STORE_PSI | PF_STORE_LAM)) {
+            coalesced();
+            const uint64_t off = cur == 2 ? off2 : off1;
+            const uint64_t st = cur == 2 ? st2 : st1;
+#pragma unroll
+            for (int r = 0; r < kRegs; ++r) {
+                const uint64_t gi = base + off + r * st;
+                if (gi & ~a.dim_mask) continue;  // replicated copies of a state smaller than a tile
+                if (a.flags & PF_STORE_PSI) psi[gi] = v[0][r];
+                if constexpr (NS > 1)
+                    if (a.flags & PF_STORE_LAM) lam[gi] = v[1][r];
+            }
+        }
+    }
+
+    // Fixed-order workgroup reduction of the FP64 accumulators.
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int s = 0; s < kMaxLocalSlots; ++s) {
+        if (s >= a.nslots) break;
+        double x = acc[s];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+        if (lane == 0) s_red[wave][s] = x;
+    }
+    __syncthreads();
+    for (int s = t; s < a.nslots; s += kThreads) {
+        const double sum = s < kMaxLocalSlots ? ((s_red[0][s] + s_red[1][s]) + (s_red[2][s] + s_red[3][s])) : s_imm[s];
+        a.partial[(size_t)(a.slot_base + s) * a.slot_stride + (size_t)b * a.G + g] = sum;
+    }
+}
+
+// out[b][o] = scale_o * sum over the slots mapped to o of sum_g partial[slot][b][g].
+__global__ void __launch_bounds__(256) finalize_kernel(const FinalizeArgs a)
+{
+    const int nout = 1 + 2 * a.p;
+    const int b = blockIdx.x / nout;
+    const int o = blockIdx.x % nout;
+    const int t = threadIdx.x;
+    __shared__ double red[256];
+    double total = 0.0;
+    for (int s = 0; s < a.nslots; ++s) {
+        if (a.slot_out[s] != o) continue;
+        const double *src = a.partial + (size_t)s * a.B * a.G + (size_t)b * a.G;
+        double x = 0.0;
+        for (int gg = t; gg < a.G; gg += 256) x += src[gg];
+        red[t] = x;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        total += red[0];
+        __syncthreads();
+    }
+    if (t == 0) a.out[(size_t)b * nout + o] = total * (o == 0 ? a.escale : 2.0 * a.escale);
+}
+
+// ---- cost diagonal (eq. (6)) ---------------------------------------------------------------
+constexpr int kMaxPairs = QQ_MAX_N * (QQ_MAX_N - 1) / 2;
+
+// One thread per basis index z.  Real problems: FP64 sum in the canonical order
+// (c0, then l_i for ascending i, then b_ij row-major) over the set bits of z;
+// integer problems: exact int32 sum of the same terms.
+template <bool INT, typename DT>
+__global__ void __launch_bounds__(256) cost_diag_kernel(int n, uint64_t dim, const double *ell, const int32_t *ell_i,
+                                                         int npairs, const int32_t *pij, const double *pb,
+                                                         const int32_t *pbi, double c0, int32_t c0_i, DT *out)
+{
+    __shared__ double s_ell[QQ_MAX_N];
+    __shared__ int32_t s_elli[QQ_MAX_N];
+    __shared__ uint8_t s_i[kMaxPairs], s_j[kMaxPairs];
+    __shared__ double s_b[kMaxPairs];
+    __shared__ int32_t s_bi[kMaxPairs];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        if (INT) s_elli[k] = ell_i[k];
+        else s_ell[k] = ell[k];
+    }
+    for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
+        s_i[k] = (uint8_t)pij[2 * k];
+        s_j[k] = (uint8_t)pij[2 * k + 1];
+        if (INT) s_bi[k] = pbi[k];
+        else s_b[k] = pb[k];
+    }
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) {
+        if constexpr (INT) {
+            int32_t acc = c0_i;
+            for (int i = 0; i < n; ++i) acc += ((z >> i) & 1) ? s_elli[i] : 0;
+            for (int k = 0; k < npairs; ++k) acc += (((z >> s_i[k]) & (z >> s_j[k])) & 1) ? s_bi[k] : 0;
+            out[z] = (DT)acc;
+        } else {
+            double acc = c0;
+            for (int i = 0; i < n; ++i) acc = ((z >> i) & 1) ? acc + s_ell[i] : acc;
+            for (int k = 0; k < npairs; ++k) acc = (((z >> s_i[k]) & (z >> s_j[k])) & 1) ? acc + s_b[k] : acc;
+            out[z] = (DT)acc;
+        }
+    }
+}
+
+// Per-block (min, argmin, max) of the diagonal; ties of the minimum go to the lowest index.
+template <typename DT>
+__global__ void __launch_bounds__(256) minmax_kernel(const DT *d, uint64_t dim, double *part, uint64_t *pidx)
+{
+    __shared__ double smin[256], smax[256];
+    __shared__ uint64_t sidx[256];
+    double mn = INFINITY, mx = -INFINITY;
+    uint64_t mi = ~0ull;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) {
+        const double c = (double)d[z];
+        if (c < mn) {
+            mn = c;
+            mi = z;
+        }
+        mx = fmax(mx, c);
+    }
+    const int t = threadIdx.x;
+    smin[t] = mn;
+    smax[t] = mx;
+    sidx[t] = mi;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) {
+            const double m2 = smin[t + w];
+            const uint64_t i2 = sidx[t + w];
+            if (m2 < smin[t] || (m2 == smin[t] && i2 < sidx[t])) {
+                smin[t] = m2;
+                sidx[t] = i2;
+            }
+            smax[t] = fmax(smax[t], smax[t + w]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        part[2 * blockIdx.x] = smin[0];
+        part[2 * blockIdx.x + 1] = smax[0];
+        pidx[blockIdx.x] = sidx[0];
+    }
+}
+
+template <typename DT, typename OT>
+__global__ void widen_kernel(const DT *d, uint64_t dim, OT *out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) out[z] = (OT)d[z];
+}
+
+// Per-QPU local cost tables: entry u of table m is the cost of the QPU's own
+// terms with its variables set from the bits of u (ascending variable order);
+// c0 belongs to QPU 0.  Same canonical term order as the full diagonal.
+template <bool INT, typename DT>
+__global__ void __launch_bounds__(256) local_tables_kernel(int n, const PartDesc *pd, const double *ell,
+                                                            const int32_t *ell_i, int npairs, const int32_t *pij,
+                                                            const double *pb, const int32_t *pbi, const int32_t *qpu,
+                                                            double c0, int32_t c0_i, DT *out, uint64_t total)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        int m = 0;
+        while (m + 1 < pd->nparts && e >= pd->table_off[m + 1]) ++m;
+        const uint64_t u = e - pd->table_off[m];
+        uint64_t z = 0;
+        for (int j = 0; j < pd->nvars[m]; ++j) z |= ((u >> j) & 1ull) << pd->vars[m][j];
+        if constexpr (INT) {
+            int32_t acc = m == 0 ? c0_i : 0;
+            for (int i = 0; i < n; ++i)
+                if (qpu[i] == m && ((z >> i) & 1)) acc += ell_i[i];
+            for (int k = 0; k < npairs; ++k) {
+                const int i = pij[2 * k], j = pij[2 * k + 1];
+                if (qpu[i] == m && qpu[j] == m && ((z >> i) & (z >> j) & 1)) acc += pbi[k];
+            }
+            out[e] = (DT)acc;
+        } else {
+            double acc = m == 0 ? c0 : 0.0;
+            for (int i = 0; i < n; ++i)
+                if (qpu[i] == m && ((z >> i) & 1)) acc += ell[i];
+            for (int k = 0; k < npairs; ++k) {
+                const int i = pij[2 * k], j = pij[2 * k + 1];
+                if (qpu[i] == m && qpu[j] == m && ((z >> i) & (z >> j) & 1)) acc += pb[k];
+            }
+            out[e] = (DT)acc;
+        }
+    }
+}
+
+template <typename C2>
+__global__ void prob_kernel(const C2 *psi, uint64_t dim, double *out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) {
+        const double re = (double)psi[z].x, im = (double)psi[z].y;
+        out[z] = fma(re, re, im * im);
+    }
+}
+
+// ---- top-k of |psi|^2 ------------------------------------------------------------------------
+// Order: larger probability first, equal probabilities by lower index.
+constexpr int kTopK = QQ_MAX_TOPK;
+
+__device__ __forceinline__ bool better(double p1, uint64_t i1, double p2, uint64_t i2)
+{
+    return p1 > p2 || (p1 == p2 && i1 < i2);
+}
+
+struct TopList {
+    double p[kTopK];
+    uint64_t i[kTopK];
+    __device__ void init()
+    {
+#pragma unroll
+        for (int k = 0; k < kTopK; ++k) {
+            p[k] = -1.0;
+            i[k] = ~0ull;
+        }
+    }
+    __device__ void insert(double pp, uint64_t ii)
+    {
+        if (!better(pp, ii, p[kTopK - 1], i[kTopK - 1])) return;
+        p[kTopK - 1] = pp;
+        i[kTopK - 1] = ii;
+#pragma unroll
+        for (int k = kTopK - 1; k > 0; --k) {
+            if (better(p[k], i[k], p[k - 1], i[k - 1])) {
+                const double tp = p[k];
+                p[k] = p[k - 1];
+                p[k - 1] = tp;
+                const uint64_t ti = i[k];
+                i[k] = i[k - 1];
+                i[k - 1] = ti;
+            }
+        }
+    }
+};
+
+// k rounds of a workgroup tournament over the per-thread sorted lists.
+__device__ void tournament(TopList &L, int k, double *outp, uint64_t *outi)
+{
+    __shared__ double sp[256];
+    __shared__ uint64_t si[256];
+    __shared__ int sw[256];
+    const int t = threadIdx.x;
+    int head = 0;
+    for (int round = 0; round < k; ++round) {
+        double hp = -1.0;
+        uint64_t hi = ~0ull;
+#pragma unroll
+        for (int q = 0; q < kTopK; ++q)
+            if (q == head) {
+                hp = L.p[q];
+                hi = L.i[q];
+            }
+        sp[t] = hp;
+        si[t] = hi;
+        sw[t] = t;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w && better(sp[t + w], si[t + w], sp[t], si[t])) {
+                sp[t] = sp[t + w];
+                si[t] = si[t + w];
+                sw[t] = sw[t + w];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            outp[round] = sp[0];
+            outi[round] = si[0];
+        }
+        if (sw[0] == t) ++head;
+        __syncthreads();
+    }
+}
+
+template <typename C2>
+__global__ void __launch_bounds__(256) topk_stage1(const C2 *psi, uint64_t dim, int k, double *cp, uint64_t *ci)
+{
+    TopList L;
+    L.init();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) {
+        const double re = (double)psi[z].x, im = (double)psi[z].y;
+        L.insert(fma(re, re, im * im), z);
+    }
+    tournament(L, k, cp + (size_t)blockIdx.x * k, ci + (size_t)blockIdx.x * k);
+}
+
+template <typename DT>
+__global__ void __launch_bounds__(256) topk_stage2(const double *cp, const uint64_t *ci, int ncand, int k,
+                                                    const DT *diag, uint64_t *oi, double *op, double *oc)
+{
+    __shared__ double fp[kTopK];
+    __shared__ uint64_t fi[kTopK];
+    TopList L;
+    L.init();
+    for (int e = threadIdx.x; e < ncand; e += blockDim.x) L.insert(cp[e], ci[e]);
+    tournament(L, k, fp, fi);
+    __syncthreads();
+    if (threadIdx.x < k) {
+        oi[threadIdx.x] = fi[threadIdx.x];
+        op[threadIdx.x] = fp[threadIdx.x];
+        oc[threadIdx.x] = (double)diag[fi[threadIdx.x]];
+    }
+}
+
+template <typename R, int NS>
+hipError_t launch_pass_t(const PassArgs &a, int diag_type, hipStream_t s)
+{
+    const dim3 grid((unsigned)(a.B * a.G)), block(kThreads);
+    switch (diag_type) {
+    case DIAG_F64: hipLaunchKernelGGL((pass_kernel<R, NS, double>), grid, block, 0, s, a); break;
+    case DIAG_I32: hipLaunchKernelGGL((pass_kernel<R, NS, int32_t>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((pass_kernel<R, NS, int16_t>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+unsigned grid_for(uint64_t work, unsigned cap = 8192)
+{
+    uint64_t g = (work + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_pass(const PassArgs &a, bool c128, int nstates, int diag_type, hipStream_t s)
+{
+    if (c128) return nstates > 1 ? launch_pass_t<double, 2>(a, diag_type, s) : launch_pass_t<double, 1>(a, diag_type, s);
+    return nstates > 1 ? launch_pass_t<float, 2>(a, diag_type, s) : launch_pass_t<float, 1>(a, diag_type, s);
+}
+
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)(a.B * (1 + 2 * a.p))), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_diag(int n, int diag_type, const double *d_ell, const int32_t *d_ell_i, int npairs,
+                            const int32_t *d_pair_ij, const double *d_pair_b, const int32_t *d_pair_bi, double c0,
+                            int32_t c0_i, void *d_out, uint64_t dim, hipStream_t s)
+{
+    const dim3 grid(grid_for(dim, 65536)), block(256);
+    switch (diag_type) {
+    case DIAG_F64:
+        hipLaunchKernelGGL((cost_diag_kernel<false, double>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs,
+                           d_pair_ij, d_pair_b, d_pair_bi, c0, c0_i, static_cast<double *>(d_out));
+        break;
+    case DIAG_I32:
+        hipLaunchKernelGGL((cost_diag_kernel<true, int32_t>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs,
+                           d_pair_ij, d_pair_b, d_pair_bi, c0, c0_i, static_cast<int32_t *>(d_out));
+        break;
+    default:
+        hipLaunchKernelGGL((cost_diag_kernel<true, int16_t>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs,
+                           d_pair_ij, d_pair_b, d_pair_bi, c0, c0_i, static_cast<int16_t *>(d_out));
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(const void *d_diag, int diag_type, uint64_t dim, double *d_part, uint64_t *d_idx,
+                         int nblocks, hipStream_t s)
+{
+    switch (diag_type) {
+    case DIAG_F64:
+        hipLaunchKernelGGL(minmax_kernel<double>, dim3(nblocks), dim3(256), 0, s,
+                           static_cast<const double *>(d_diag), dim, d_part, d_idx);
+        break;
+    case DIAG_I32:
+        hipLaunchKernelGGL(minmax_kernel<int32_t>, dim3(nblocks), dim3(256), 0, s,
+                           static_cast<const int32_t *>(d_diag), dim, d_part, d_idx);
+        break;
+    default:
+        hipLaunchKernelGGL(minmax_kernel<int16_t>, dim3(nblocks), dim3(256), 0, s,
+                           static_cast<const int16_t *>(d_diag), dim, d_part, d_idx);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_widen_diag(const void *d_diag, int diag_type, uint64_t dim, void *d_out, hipStream_t s)
+{
+    const dim3 grid(grid_for(dim)), block(256);
+    switch (diag_type) {
+    case DIAG_F64:
+        hipLaunchKernelGGL((widen_kernel<double, double>), grid, block, 0, s, static_cast<const double *>(d_diag),
+                           dim, static_cast<double *>(d_out));
+        break;
+    case DIAG_I32:
+        hipLaunchKernelGGL((widen_kernel<int32_t, int32_t>), grid, block, 0, s,
+                           static_cast<const int32_t *>(d_diag), dim, static_cast<int32_t *>(d_out));
+        break;
+    default:
+        hipLaunchKernelGGL((widen_kernel<int16_t, int32_t>), grid, block, 0, s,
+                           static_cast<const int16_t *>(d_diag), dim, static_cast<int32_t *>(d_out));
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_probabilities(const void *psi, bool c128, uint64_t dim, double *out, hipStream_t s)
+{
+    const dim3 grid(grid_for(dim)), block(256);
+    if (c128)
+        hipLaunchKernelGGL(prob_kernel<double2>, grid, block, 0, s, static_cast<const double2 *>(psi), dim, out);
+    else
+        hipLaunchKernelGGL(prob_kernel<float2>, grid, block, 0, s, static_cast<const float2 *>(psi), dim, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk(const void *psi, bool c128, uint64_t dim, int k, const void *diag, int diag_type,
+                       uint64_t *d_idx, double *d_prob, double *d_cost, void *scratch, int nblocks, hipStream_t s)
+{
+    double *cp = static_cast<double *>(scratch);
+    uint64_t *ci = reinterpret_cast<uint64_t *>(cp + (size_t)nblocks * k);
+    if (c128)
+        hipLaunchKernelGGL(topk_stage1<double2>, dim3(nblocks), dim3(256), 0, s, static_cast<const double2 *>(psi),
+                           dim, k, cp, ci);
+    else
+        hipLaunchKernelGGL(topk_stage1<float2>, dim3(nblocks), dim3(256), 0, s, static_cast<const float2 *>(psi),
+                           dim, k, cp, ci);
+    switch (diag_type) {
+    case DIAG_F64:
+        hipLaunchKernelGGL(topk_stage2<double>, dim3(1), dim3(256), 0, s, cp, ci, nblocks * k, k,
+                           static_cast<const double *>(diag), d_idx, d_prob, d_cost);
+        break;
+    case DIAG_I32:
+        hipLaunchKernelGGL(topk_stage2<int32_t>, dim3(1), dim3(256), 0, s, cp, ci, nblocks * k, k,
+                           static_cast<const int32_t *>(diag), d_idx, d_prob, d_cost);
+        break;
+    default:
+        hipLaunchKernelGGL(topk_stage2<int16_t>, dim3(1), dim3(256), 0, s, cp, ci, nblocks * k, k,
+                           static_cast<const int16_t *>(diag), d_idx, d_prob, d_cost);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_local_tables(int n, int diag_type, const PartDesc *d_pd, const double *d_ell,
+                               const int32_t *d_ell_i, int npairs, const int32_t *d_pair_ij, const double *d_pair_b,
+                               const int32_t *d_pair_bi, const int32_t *d_qpu, double c0, int32_t c0_i, void *d_tables,
+                               uint64_t total, hipStream_t s)
+{
+    const dim3 grid(grid_for(total)), block(256);
+    switch (diag_type) {
+    case DIAG_F64:
+        hipLaunchKernelGGL((local_tables_kernel<false, double>), grid, block, 0, s, n, d_pd, d_ell, d_ell_i, npairs,
+                           d_pair_ij, d_pair_b, d_pair_bi, d_qpu, c0, c0_i, static_cast<double *>(d_tables), total);
+        break;
+    case DIAG_I32:
+        hipLaunchKernelGGL((local_tables_kernel<true, int32_t>), grid, block, 0, s, n, d_pd, d_ell, d_ell_i, npairs,
+                           d_pair_ij, d_pair_b, d_pair_bi, d_qpu, c0, c0_i, static_cast<int32_t *>(d_tables), total);
+        break;
+    default:
+        hipLaunchKernelGGL((local_tables_kernel<true, int16_t>), grid, block, 0, s, n, d_pd, d_ell, d_ell_i, npairs,
+                           d_pair_ij, d_pair_b, d_pair_bi, d_qpu, c0, c0_i, static_cast<int16_t *>(d_tables), total);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qq

@@ -1,0 +1,254 @@
+"""ctypes binding of libqaoa_qubo.so: one Python function per C-ABI entry point, same names.
+
+Argument marshalling only -- every step of the computation runs in the HIP
+library.  torch is imported before the library is loaded so that both share
+one HIP runtime (the library links libamdhip64.so.7 by soname).  A missing
+library is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqaoa_qubo.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qaoa_qubo.h")
+
+QQ_OK = 0
+QQ_E_INVALID = -1
+QQ_E_ALLOCATION = -2
+QQ_E_TOO_LARGE = -3
+QQ_E_WORKSPACE = -4
+QQ_E_DEVICE = -5
+QQ_E_NOMEM = -6
+QQ_E_UNSUPPORTED = -7
+STATUS_NAMES = {0: "QQ_OK", -1: "QQ_E_INVALID", -2: "QQ_E_ALLOCATION", -3: "QQ_E_TOO_LARGE",
+                -4: "QQ_E_WORKSPACE", -5: "QQ_E_DEVICE", -6: "QQ_E_NOMEM", -7: "QQ_E_UNSUPPORTED"}
+
+QQ_ENERGY = 1
+QQ_GRAD = 2
+QQ_PARTITIONED = 4
+QQ_C128 = 8
+QQ_PARAMS_ON_DEVICE = 16
+QQ_OUT_ON_DEVICE = 32
+
+QQ_MAX_N = 34
+QQ_MAX_P = 64
+QQ_MAX_QPUS = 16
+QQ_MAX_TOPK = 16
+
+
+class QQError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class QQInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("is_integer", ctypes.c_int), ("diag_bytes", ctypes.c_int),
+                ("num_qpus", ctypes.c_int), ("c0", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("sigma_c", ctypes.c_double), ("cmin", ctypes.c_double), ("cmax", ctypes.c_double),
+                ("argmin_index", ctypes.c_uint64), ("nonzero_couplings", ctypes.c_int64),
+                ("cross_terms", ctypes.c_int64)]
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_int = ctypes.c_int
+
+SIGNATURES = {
+    "qq_last_error": ([], ctypes.c_char_p),
+    "qq_abi_version": ([], _int),
+    "qq_device_count": ([ctypes.POINTER(_int)], _int),
+    "qq_problem_create": ([_int, _dp, _dp, ctypes.c_double, _int, _vp, ctypes.POINTER(_vp)], _int),
+    "qq_problem_destroy": ([_vp], _int),
+    "qq_problem_info": ([_vp, ctypes.POINTER(QQInfo)], _int),
+    "qq_coefficients": ([_vp, _dp, _dp, _dp, _dp, _dp], _int),
+    "qq_cost_diagonal": ([_vp, _vp, _int, _vp], _int),
+    "qq_set_allocation": ([_vp, _int, _i32p, _i32p, _i64p, _i64p], _int),
+    "qq_workspace_size": ([_vp, _int, _int, _int, _szp], _int),
+    "qq_evaluate": ([_vp, _int, _int, _vp, _int, _vp, ctypes.c_size_t, _vp, _vp, _vp], _int),
+    "qq_state": ([_vp, _int, _vp, _int, _vp, _vp], _int),
+    "qq_probabilities": ([_vp, _int, _vp, _int, _vp, _vp], _int),
+    "qq_topk": ([_vp, _int, _vp, _int, _int, _u64p, _dp, _dp, _vp], _int),
+    "qq_evaluate_plain": ([_vp, _int, _dp, _int, _vp, _dp, _dp], _int),
+}
+
+_LIB = None
+
+
+def header_symbols():
+    """Names of every function the public header declares."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qq_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """Load the library (importing torch first).  Raises if it is not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run python -m paper_2606_26297_amd.build)")
+    import torch  # noqa: F401  -- shares its HIP runtime with the library
+
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = L
+    return L
+
+
+def _check(status: int):
+    if status != QQ_OK:
+        raise QQError(status, lib().qq_last_error().decode())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, ctype=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+# ---- one wrapper per entry point ------------------------------------------------------------
+
+def qq_last_error() -> str:
+    return lib().qq_last_error().decode()
+
+
+def qq_abi_version() -> int:
+    return lib().qq_abi_version()
+
+
+def qq_device_count() -> int:
+    c = _int(0)
+    _check(lib().qq_device_count(ctypes.byref(c)))
+    return c.value
+
+
+def qq_problem_create(n, H, f=None, c0=0.0, device=0, stream=None):
+    H = _f64(H).reshape(-1)
+    fp = None
+    if f is not None:
+        f = _f64(f)
+        fp = _ptr(f)
+    out = _vp()
+    _check(lib().qq_problem_create(int(n), _ptr(H), fp, float(c0), int(device), _stream_ptr(stream),
+                                   ctypes.byref(out)))
+    return out
+
+
+def qq_problem_destroy(handle):
+    _check(lib().qq_problem_destroy(handle))
+
+
+def qq_problem_info(handle) -> QQInfo:
+    info = QQInfo()
+    _check(lib().qq_problem_info(handle, ctypes.byref(info)))
+    return info
+
+
+def qq_coefficients(handle, n):
+    ell = np.zeros(n)
+    b = np.zeros((n, n))
+    h = np.zeros(n)
+    J = np.zeros((n, n))
+    alpha = ctypes.c_double(0.0)
+    _check(lib().qq_coefficients(handle, _ptr(ell), _ptr(b), ctypes.byref(alpha), _ptr(h), _ptr(J)))
+    return ell, b, alpha.value, h, J
+
+
+def qq_cost_diagonal(handle, out, flags=0, stream=None):
+    """out: numpy array (int32 or float64) or a device tensor with QQ_OUT_ON_DEVICE."""
+    ptr = _dev_ptr(out) if flags & QQ_OUT_ON_DEVICE else out.ctypes.data_as(_vp)
+    _check(lib().qq_cost_diagonal(handle, ptr, int(flags), _stream_ptr(stream)))
+    return out
+
+
+def qq_set_allocation(handle, num_qpus, qpu_of_var, capacities=None):
+    q = np.ascontiguousarray(qpu_of_var, dtype=np.int32)
+    cap = None if capacities is None else np.ascontiguousarray(capacities, dtype=np.int32)
+    cross = ctypes.c_int64(0)
+    remote = ctypes.c_int64(0)
+    _check(lib().qq_set_allocation(handle, int(num_qpus), _ptr(q, ctypes.c_int32),
+                                   None if cap is None else _ptr(cap, ctypes.c_int32), ctypes.byref(cross),
+                                   ctypes.byref(remote)))
+    return cross.value, remote.value
+
+
+def qq_workspace_size(handle, p, batch, flags) -> int:
+    s = ctypes.c_size_t(0)
+    _check(lib().qq_workspace_size(handle, int(p), int(batch), int(flags), ctypes.byref(s)))
+    return s.value
+
+
+def qq_evaluate(handle, p, batch, params, flags, workspace, ws_bytes, stream, energy_out, grad_out):
+    """params / energy_out / grad_out: numpy arrays, or device tensors with the *_ON_DEVICE flags."""
+    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
+    if flags & QQ_OUT_ON_DEVICE:
+        ep = _dev_ptr(energy_out)
+        gp = _dev_ptr(grad_out) if grad_out is not None else None
+    else:
+        ep = energy_out.ctypes.data_as(_vp)
+        gp = grad_out.ctypes.data_as(_vp) if grad_out is not None else None
+    wp = None if workspace is None else _dev_ptr(workspace)
+    _check(lib().qq_evaluate(handle, int(p), int(batch), pp, int(flags), wp, int(ws_bytes), _stream_ptr(stream), ep,
+                             gp))
+
+
+def qq_state(handle, p, params, flags, psi_out, stream=None):
+    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
+    op = _dev_ptr(psi_out) if flags & QQ_OUT_ON_DEVICE else psi_out.ctypes.data_as(_vp)
+    _check(lib().qq_state(handle, int(p), pp, int(flags), op, _stream_ptr(stream)))
+    return psi_out
+
+
+def qq_probabilities(handle, p, params, flags, prob_out, stream=None):
+    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
+    op = _dev_ptr(prob_out) if flags & QQ_OUT_ON_DEVICE else prob_out.ctypes.data_as(_vp)
+    _check(lib().qq_probabilities(handle, int(p), pp, int(flags), op, _stream_ptr(stream)))
+    return prob_out
+
+
+def qq_topk(handle, p, params, flags, k, stream=None):
+    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
+    idx = np.zeros(k, dtype=np.uint64)
+    prob = np.zeros(k)
+    cost = np.zeros(k)
+    _check(lib().qq_topk(handle, int(p), pp, int(flags), int(k), _ptr(idx, ctypes.c_uint64), _ptr(prob),
+                         _ptr(cost), _stream_ptr(stream)))
+    return idx, prob, cost
+
+
+def qq_evaluate_plain(handle, p, params, flags, stream=None):
+    x = _f64(params).reshape(-1)
+    e = np.zeros(1)
+    g = np.zeros(2 * p)
+    _check(lib().qq_evaluate_plain(handle, int(p), _ptr(x), int(flags), _stream_ptr(stream), _ptr(e), _ptr(g)))
+    return float(e[0]), g

@@ -1,0 +1,131 @@
+"""Python convenience layer over the C ABI: a Problem handle and a torch.autograd.Function.
+
+Every computation happens in libqaoa_qubo.so; this module only manages
+handles, buffers and streams.  torch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import native as N
+
+
+class Problem:
+    """A QUBO in the dense input form F(z) = c0 + f^T z + z^T H z (eq. (2)), resident on one GPU."""
+
+    def __init__(self, H, f=None, c0=0.0, device=0):
+        H = np.asarray(H, dtype=np.float64)
+        self.n = int(H.shape[0])
+        self.device = device
+        self.handle = N.qq_problem_create(self.n, H, f, c0, device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            N.qq_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> N.QQInfo:
+        return N.qq_problem_info(self.handle)
+
+    def coefficients(self):
+        """(l, b, alpha, h, J) of eq. (4)-(5) and eq. (9)."""
+        return N.qq_coefficients(self.handle, self.n)
+
+    def diagonal(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.int32 if self.info.is_integer else np.float64)
+        return N.qq_cost_diagonal(self.handle, out)
+
+    def set_allocation(self, qpu_of_var, num_qpus=None, capacities=None):
+        q = np.asarray(qpu_of_var, dtype=np.int32)
+        M = int(q.max()) + 1 if num_qpus is None else int(num_qpus)
+        return N.qq_set_allocation(self.handle, M, q, capacities)
+
+    def workspace_size(self, p, batch, flags) -> int:
+        return N.qq_workspace_size(self.handle, p, batch, flags)
+
+    def evaluate(self, params, grad=False, c128=False, partitioned=False, workspace=None):
+        """Energies (and gradients) for params[B, 2p] given as numpy (host path) or a CUDA tensor (device path)."""
+        import torch
+
+        flags = N.QQ_ENERGY | (N.QQ_GRAD if grad else 0) | (N.QQ_C128 if c128 else 0) | \
+            (N.QQ_PARTITIONED if partitioned else 0)
+        if isinstance(params, torch.Tensor) and params.is_cuda:
+            x = params.detach().to(torch.float64).contiguous()
+            B, twop = x.shape
+            p = twop // 2
+            flags |= N.QQ_PARAMS_ON_DEVICE | N.QQ_OUT_ON_DEVICE
+            e = torch.empty(B, dtype=torch.float64, device=x.device)
+            g = torch.empty(B, twop, dtype=torch.float64, device=x.device) if grad else None
+            ws_bytes = self.workspace_size(p, B, flags)
+            ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=x.device)
+            N.qq_evaluate(self.handle, p, B, x, flags, ws, ws.numel(), torch.cuda.current_stream(x.device), e, g)
+            return (e, g) if grad else e
+        x = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+        B, twop = x.shape
+        p = twop // 2
+        e = np.empty(B)
+        g = np.empty((B, twop)) if grad else None
+        N.qq_evaluate(self.handle, p, B, x, flags, None, 0, None, e, g)
+        return (e, g) if grad else e
+
+    def state(self, params, c128=False, partitioned=False):
+        x = np.ascontiguousarray(params, dtype=np.float64).ravel()
+        p = x.shape[0] // 2
+        flags = (N.QQ_C128 if c128 else 0) | (N.QQ_PARTITIONED if partitioned else 0)
+        out = np.empty(1 << self.n, dtype=np.complex128 if c128 else np.complex64)
+        return N.qq_state(self.handle, p, x, flags, out)
+
+    def probabilities(self, params, c128=False):
+        x = np.ascontiguousarray(params, dtype=np.float64).ravel()
+        out = np.empty(1 << self.n)
+        return N.qq_probabilities(self.handle, x.shape[0] // 2, x, N.QQ_C128 if c128 else 0, out)
+
+    def topk(self, params, k=10, c128=False):
+        x = np.ascontiguousarray(params, dtype=np.float64).ravel()
+        return N.qq_topk(self.handle, x.shape[0] // 2, x, N.QQ_C128 if c128 else 0, k)
+
+    def evaluate_plain(self, params, grad=False):
+        x = np.ascontiguousarray(params, dtype=np.float64).ravel()
+        return N.qq_evaluate_plain(self.handle, x.shape[0] // 2, x, N.QQ_GRAD if grad else N.QQ_ENERGY)
+
+
+def _make_autograd():
+    import torch
+
+    class QAOAEnergy(torch.autograd.Function):
+        """E(x) for x[B, 2p] on the GPU; backward returns g_out[:, None] * dE/dx from the adjoint sweep."""
+
+        @staticmethod
+        def forward(ctx, params, problem, c128=False):
+            need = params.requires_grad
+            if need:
+                e, g = problem.evaluate(params, grad=True, c128=c128)
+                ctx.save_for_backward(g)
+            else:
+                e = problem.evaluate(params, grad=False, c128=c128)
+            return e
+
+        @staticmethod
+        def backward(ctx, g_out):
+            (g,) = ctx.saved_tensors
+            return g_out[:, None] * g, None, None
+
+    return QAOAEnergy
+
+
+_QAOAEnergy = None
+
+
+def qaoa_energy(params, problem: Problem, c128: bool = False):
+    """Differentiable QAOA energy: params[B, 2p] (CUDA tensor) -> energies[B]."""
+    global _QAOAEnergy
+    if _QAOAEnergy is None:
+        _QAOAEnergy = _make_autograd()
+    return _QAOAEnergy.apply(params, problem, c128)
