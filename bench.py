@@ -1,0 +1,197 @@
+"""Benchmark: batched complex64 QAOA energy + adjoint gradient at n = 28, p = 8.
+
+Workload (one "step"): the 28-node random 3-regular QUBO (edge weights U[0,1],
+linear terms N(0, 0.5^2), seeded), p = 8, 64 multi-start parameter sets drawn
+U[0, pi]; one step evaluates J(x) and all 16 partial derivatives for every
+start through the C ABI (qq_evaluate, QQ_GRAD, device-resident params and
+outputs), in waves of `--wave` starts.  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+Extra measurements in the same run:
+  * per-launch HIP-event timing of every pass kernel during the timed steps
+    (roofline of the dominant kernel: algorithmic bytes / launch time vs 8 TB/s);
+  * the plain complex128 per-gate path (one kernel per gate, one parameter
+    set per call) on the same GPU, for the speed-up ratio;
+  * a sampled parity check of the timed path against the complex128 fused path;
+  * the CPU oracle (single thread, FP64) on a bounded sample of the same
+    instance family, scaled to n = 28.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QAOA energy+grad evals/s and HBM GB/s at n=28 p=8, <=1e-5 rel vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_26297_amd", "csrc", "qq_kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel_name: str):
+    """Counter-derived HBM bytes per launch from profiles/, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_src_sha256_16") != kernel_hash():
+        return None
+    entry = t.get("kernels", {}).get(kernel_name)
+    return None if entry is None else entry.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n_sample=22, starts=2, p=8):
+    """Oracle energy + adjoint gradient for `starts` starts on an n_sample-node instance of the same family."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2606_26297_amd import workloads as W
+
+    inst = W.regular_graph_qubo(n_sample, W.INSTANCE_SEEDS[3])
+    d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+    x = W.random_params(p, starts, W.PARAM_SEEDS[3])
+    t0 = time.perf_counter()
+    for b in range(starts):
+        O.gradient(d, x[b])
+    dt = time.perf_counter() - t0
+    scale = (2.0 ** (28 - n_sample)) * 28.0 / n_sample  # work grows as n 2^n
+    per_eval_28 = dt / starts * scale
+    return {"value": 1.0 / per_eval_28, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{starts} energy+adjoint-gradient evaluations (p={p}) of a {n_sample}-node 3-regular "
+                      f"instance of the same generator, single-threaded FP64 C, {dt:.1f} s; scaled to n=28 by "
+                      f"2^{28 - n_sample}*28/{n_sample} (work ~ n 2^n)",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--wave", type=int, default=16, help="starts per qq_evaluate call")
+    ap.add_argument("--starts", type=int, default=64)
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the hot path of this build runs on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd import workloads as W
+    from paper_2606_26297_amd.qaoa import Problem
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    inst, x = W.workload3(batch=args.starts, p=args.p, n=args.n)
+    pb = Problem(inst.H, inst.f, inst.c0, device=0)
+    p, S, B = args.p, args.starts, args.wave
+    assert S % B == 0
+    flags = N.QQ_ENERGY | N.QQ_GRAD | N.QQ_PARAMS_ON_DEVICE | N.QQ_OUT_ON_DEVICE
+    xt = torch.tensor(x, dtype=torch.float64, device=dev)
+    e_out = torch.empty(S, dtype=torch.float64, device=dev)
+    g_out = torch.empty(S, 2 * p, dtype=torch.float64, device=dev)
+    ws_bytes = pb.workspace_size(p, B, flags)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        for w in range(S // B):
+            N.qq_evaluate(pb.handle, p, B, xt[w * B:(w + 1) * B], flags, ws, ws_bytes, stream,
+                          e_out[w * B:(w + 1) * B], g_out[w * B:(w + 1) * B])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    N.qq_profile_enable(True)
+    N.qq_profile_read()  # clear
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    N.qq_profile_enable(False)
+    recs = N.qq_profile_read()
+    wall = t1 - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    value = S * args.steps / wall
+
+    # roofline of the dominant kernel (the instantiation with the largest total time)
+    by_kind = {}
+    for r in recs:
+        k = N.kernel_name(r)
+        d = by_kind.setdefault(k, {"ms": 0.0, "bytes": 0.0, "launches": 0})
+        d["ms"] += r["ms"]
+        d["bytes"] += r["bytes"]
+        d["launches"] += 1
+    dom = max(by_kind, key=lambda k: by_kind[k]["ms"])
+    dk = by_kind[dom]
+    achieved = dk["bytes"] / (dk["ms"] / 1000.0) / 1e9
+    traffic = load_traffic(dom)
+    step_bytes = sum(d["bytes"] for d in by_kind.values()) / args.steps
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "launches": dk["launches"], "avg_launch_ms": round(dk["ms"] / dk["launches"], 4),
+                "algorithmic_bytes_per_launch": dk["bytes"] / dk["launches"]}
+    kernels = {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
+                   "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in by_kind.items()}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+           "config": {"workload": f"regular3_n{args.n}_p{p}_starts{S}", "n": args.n, "p": p, "starts": S,
+                      "wave": B, "state": "complex64", "accumulators": "fp64"},
+           "hbm_GBps_step": round(step_bytes / (ms_per_step / 1000.0) / 1e9, 1),
+           "algorithmic_bytes_per_eval": step_bytes / S,
+           "roofline": roofline, "kernels": kernels}
+
+    if not args.no_check:
+        # sampled parity at full size: complex64 timed path vs the complex128 fused path (both GPU)
+        e64 = e_out[:2].cpu().numpy()
+        g64 = g_out[:2].cpu().numpy()
+        e128, g128 = pb.evaluate(x[:2], grad=True, c128=True)
+        sig = pb.info.sigma_c
+        out["check"] = {"vs": "complex128 fused path, starts 0-1",
+                        "energy_rel": float(np.max(np.abs(e64 - e128) / np.maximum(np.abs(e128), sig))),
+                        "grad_rel": float(np.max(np.abs(g64 - g128)) / np.max(np.abs(g128)))}
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.evaluate_plain(x[0], grad=True)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out["plain_fp64"] = {"evals_per_s": round(1.0 / tp, 4), "seconds_per_eval": round(tp, 3),
+                             "speedup": round(value * tp, 2),
+                             "definition": "complex128, one kernel per gate (phase per layer, RX per qubit and "
+                                           "layer, energy reduction, unfused adjoint), one parameter set per call"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,33 @@ qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int 
 qq_status qq_evaluate_plain(qq_problem *prob, int p, const double *params, int flags, void *stream,
                             double *energy_out, double *grad_out);
 
+/*
+ * Per-launch timing of the pass kernels, for measurement tools.
+ * qq_profile_enable(1) makes every later evaluation record a pair of HIP
+ * events around each kernel launch (on the stream the kernel runs on) plus
+ * the launch's algorithmic HBM bytes (state reads/writes and cost-diagonal
+ * reads the method needs, counted per state).  qq_profile_read()
+ * synchronises those events, copies up to `max` records (oldest first) to
+ * `out`, stores the number of records in `count` and clears the log.
+ * Profiling is process-wide and off by default; it is not thread-safe.
+ */
+typedef struct {
+    int kind;       /* 1: forward pass (one state), 2: adjoint pass (psi and lambda), 3: final reduction */
+    int pass_kind;  /* complex64 specialised kernel: 0 first, 1 mid, 2 turn, 3 last, 4 last+adjoint seed,
+                       5 adjoint mid, 6 adjoint turn, 7 adjoint last; -1: generic pass kernel */
+    int high;       /* 1 when the pass mixes qubits above 11 (strided tile) */
+    int full;       /* 1 when every register-group bit of the tile is mixed (compile-time masks) */
+    int diag_bytes; /* bytes per cost-diagonal entry the kernel reads */
+    int c128;       /* 1 for complex128 state */
+    int n;          /* qubits */
+    int batch;      /* states in the launch */
+    double bytes;   /* algorithmic bytes moved by the launch */
+    double ms;      /* event-timed duration */
+} qq_launch_record;
+
+qq_status qq_profile_enable(int enable);
+qq_status qq_profile_read(qq_launch_record *out, int max, int *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -43,11 +44,22 @@ qq_status fail(qq_status st, const char *fmt, ...)
     } while (0)
 
 constexpr double kTwo31 = 2147483648.0;
+// The specialised kernels address a lane's amplitudes with a 32-bit byte offset
+// of at most (15 + 3 * 2^pos8) * 8 bytes, which fits while pos8 <= 27, i.e. n <= 31.
+constexpr int kFastMaxN = 31;
 constexpr double kTwo15 = 32768.0;
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 int diag_bytes_of(int t) { return t == DIAG_F64 ? 8 : t == DIAG_I32 ? 4 : 2; }
+
+struct ProfRec {
+    hipEvent_t start, stop;
+    qq_launch_record meta;
+};
+bool g_prof = false;
+bool g_force_generic = false;  // QQ_GENERIC_PASSES=1: use the generic pass kernel everywhere
+std::vector<ProfRec> g_prof_log;
 
 struct DevBuf {
     void *p = nullptr;
@@ -107,34 +119,47 @@ namespace {
 
 // ---- pass planning -------------------------------------------------------------------------
 // Qubit sets mixed by one pass.  Set 0 is qubits 0..11 (a contiguous tile);
-// each further set is up to 8 qubits placed in the upper 8 bits of a high
-// tile whose low 4 bits are qubits 0..3.
+// every further set is a high tile: qubits 0..3 (passive) plus two runs of
+// four qubits, pos4..pos4+3 and pos8..pos8+3, of which the `active` tile bits
+// are mixed.
 struct SetDesc {
     int high;
-    int pos4;
-    int hshift;
+    int pos4, pos8;
     uint16_t active;
 };
 
+// High-set layout.  When the qubits above 11 split into full sets (n - 12 a
+// multiple of 8) they are cut into 4-qubit runs R_0..R_{m-1} and run i is paired
+// with run m-1-i: the pairing measured fastest on MI355X, since it spreads the
+// qubits of the largest address strides over both high sets.  Otherwise each
+// set is a contiguous 8-qubit window [h, h+8), the last one shifted down to end
+// at n with its already-covered qubits inactive.
 std::vector<SetDesc> make_sets(int n)
 {
     std::vector<SetDesc> sets;
     if (n <= kTileBits) {
-        sets.push_back({0, 4, 0, (uint16_t)((1u << n) - 1u)});
+        sets.push_back({0, 4, 8, (uint16_t)((1u << n) - 1u)});
         return sets;
     }
-    sets.push_back({0, 4, 0, 0x0fff});
+    sets.push_back({0, 4, 8, 0x0fff});
+    if ((n - kTileBits) % 8 == 0) {
+        const int m = (n - kTileBits) / 4;
+        for (int i = 0; i < m / 2; ++i) sets.push_back({1, kTileBits + 4 * i, kTileBits + 4 * (m - 1 - i), 0x0ff0});
+        return sets;
+    }
     for (int q0 = kTileBits; q0 < n; q0 += 8) {
         const int q1 = std::min(n, q0 + 8);
         const int h = std::min(q0, n - 8);
         uint16_t act = 0;
         for (int q = q0; q < q1; ++q) act |= (uint16_t)(1u << (4 + q - h));
-        sets.push_back({1, h, h - 4, act});
+        sets.push_back({1, h, h + 4, act});
     }
     return sets;
 }
 
 struct PassPlan {
+    int fkind = -1;  // FastPassKind of this pass (multi-pass plans)
+    int fk = 0;      // its layer index
     int set = 0;
     uint32_t flags = 0;
     int nstates = 1;
@@ -239,6 +264,7 @@ Plan make_plan(int n, int p, int mode)
     } else {
         {
             PassPlan pp;
+            pp.fkind = FK_FIRST;
             pp.set = order(0)[0];
             pp.flags = PF_INIT | PF_STORE_PSI;
             pp.ops.push_back(op_phase(0, false, 1, part));
@@ -251,10 +277,13 @@ Plan make_plan(int n, int p, int mode)
                 const int set = o[idx];
                 PassPlan pp;
                 pp.set = set;
+                pp.fk = k;
                 if (idx < s - 1) {
+                    pp.fkind = FK_MID;
                     pp.flags = PF_LOAD_PSI | PF_STORE_PSI;
                     pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
                 } else if (k < p - 1) {
+                    pp.fkind = FK_TURN;
                     pp.flags = PF_LOAD_PSI | PF_STORE_PSI;
                     pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
                     pp.ops.push_back(op_phase(k + 1, false, 1, part));
@@ -262,12 +291,14 @@ Plan make_plan(int n, int p, int mode)
                 } else if (grad) {
                     // psi in memory stays the state before this set's mixer; lambda is
                     // formed in registers and leaves with the set already un-mixed.
+                    pp.fkind = FK_LASTG;
                     pp.flags = PF_LOAD_PSI | PF_STORE_LAM;
                     pp.nstates = 2;
                     pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
                     pp.ops.push_back(op_acc(pp, OP_ENERGY_LAMBDA, k, out_energy(), 0));
                     pp.ops.push_back(op_mix(pp, k, true, act(set), 3, out_beta(k)));
                 } else {
+                    pp.fkind = FK_LAST;
                     pp.flags = PF_LOAD_PSI | (store ? PF_STORE_PSI : 0);
                     pp.ops.push_back(op_mix(pp, k, false, act(set), 1, -1));
                     if (energy) pp.ops.push_back(op_acc(pp, OP_ENERGY, k, out_energy(), 0));
@@ -284,16 +315,20 @@ Plan make_plan(int n, int p, int mode)
                     PassPlan pp;
                     pp.set = set;
                     pp.nstates = 2;
+                    pp.fk = k;
                     if (idx < s - 1) {
+                        pp.fkind = FK_BMID;
                         pp.flags = PF_LOAD_PSI | PF_LOAD_LAM | PF_STORE_PSI | PF_STORE_LAM;
                         pp.ops.push_back(op_mix(pp, k, true, act(set), 3, out_beta(k)));
                     } else if (k > 0) {
+                        pp.fkind = FK_BTURN;
                         pp.flags = PF_LOAD_PSI | PF_LOAD_LAM | PF_STORE_PSI | PF_STORE_LAM;
                         pp.ops.push_back(op_mix(pp, k, true, act(set), 3, out_beta(k)));
                         pp.ops.push_back(op_acc(pp, OP_GGAMMA, k, out_gamma(k),
                                                 (uint8_t)(OPF_UNPHASE | (part ? OPF_PARTITIONED : 0))));
                         pp.ops.push_back(op_mix(pp, k - 1, true, act(set), 3, out_beta(k - 1)));
                     } else {
+                        pp.fkind = FK_BLAST;
                         pp.flags = PF_LOAD_PSI | PF_LOAD_LAM;
                         pp.ops.push_back(op_mix(pp, 0, true, act(set), 3, out_beta(0)));
                         pp.ops.push_back(op_acc(pp, OP_GGAMMA, 0, out_gamma(0), 0));
@@ -375,6 +410,27 @@ qq_status check_device_fits(int device, size_t bytes, const char *what)
     return QQ_OK;
 }
 
+// Algorithmic HBM bytes of one pass: every state load and store, plus one
+// cost-diagonal read per operation that needs C(z) (per state; the
+// partitioned phase also reads the cross-QPU diagonal).
+double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128)
+{
+    const double es = c128 ? 16.0 : 8.0, d = diag_bytes_of(pb->diag_type);
+    const double amps = (double)pb->dim * B;
+    int moves = 0;
+    if (pp.flags & PF_LOAD_PSI) ++moves;
+    if (pp.flags & PF_LOAD_LAM) ++moves;
+    if (pp.flags & PF_STORE_PSI) ++moves;
+    if (pp.flags & PF_STORE_LAM) ++moves;
+    double diag_reads = 0;
+    for (const Op &o : pp.ops) {
+        if (o.kind == OP_PHASE || o.kind == OP_ENERGY || o.kind == OP_ENERGY_LAMBDA || o.kind == OP_GGAMMA) diag_reads += 1;
+        if ((o.kind == OP_PHASE || (o.kind == OP_GGAMMA && (o.flags & OPF_UNPHASE))) && (o.flags & OPF_PARTITIONED))
+            diag_reads += 1;
+    }
+    return amps * (moves * es + diag_reads * d);
+}
+
 // Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
 qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int B, int flags, char *ws,
                    const double *d_params, hipStream_t stream)
@@ -384,6 +440,9 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
     const size_t es = c128 ? 16 : 8;
     (void)es;
     if (plan.nslots > kMaxSlots) return fail(QQ_E_UNSUPPORTED, "plan needs %d accumulator slots (max %d)", plan.nslots, kMaxSlots);
+    // Specialised complex64 kernels serve multi-pass, non-partitioned plans.
+    const bool use_fast =
+        !c128 && plan.sets.size() > 1 && !(flags & QQ_PARTITIONED) && !g_force_generic && pb->n <= kFastMaxN;
     int slot_base = 0;
     for (const auto &pp : plan.passes) {
         if ((int)pp.ops.size() > kMaxOps) return fail(QQ_E_UNSUPPORTED, "pass has %zu ops (max %d)", pp.ops.size(), kMaxOps);
@@ -397,9 +456,10 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
         a.tiles = T;
         a.dim_mask = pb->dim - 1;
         a.pos4 = sd.pos4;
-        a.pos8 = sd.pos4 + 4;
+        a.pos8 = sd.pos8;
         a.high = sd.high;
-        a.hshift = sd.hshift;
+        a.w1 = sd.pos4 - 4;
+        a.w2 = sd.pos8 - sd.pos4 - 4;
         a.flags = pp.flags;
         a.nops = (int)pp.ops.size();
         a.nslots = (int)pp.slot_out.size();
@@ -416,7 +476,52 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
         a.cross_diag = pb->d_cross;
         a.part = pb->d_part;
         for (size_t i = 0; i < pp.ops.size(); ++i) a.ops[i] = pp.ops[i];
-        QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
+        ProfRec rec{};
+        if (g_prof) {
+            QQ_HIP(hipEventCreate(&rec.start));
+            QQ_HIP(hipEventCreate(&rec.stop));
+            QQ_HIP(hipEventRecord(rec.start, stream));
+        }
+        if (use_fast && pp.fkind >= 0) {
+            FastPassParams fp;
+            fp.B = B;
+            fp.G = L.G;
+            fp.p = p;
+            fp.k = pp.fk;
+            fp.tiles = T;
+            fp.dim_mask = pb->dim - 1;
+            fp.pos4 = sd.pos4;
+            fp.pos8 = sd.pos8;
+            fp.w1 = sd.pos4 - 4;
+            fp.w2 = sd.pos8 - sd.pos4 - 4;
+            fp.active = sd.active;
+            fp.store_psi = (pp.flags & PF_STORE_PSI) ? 1 : 0;
+            fp.slot_base = slot_base;
+            fp.slot_stride = B * L.G;
+            fp.amp0 = a.amp0;
+            fp.params = d_params;
+            fp.diag = pb->d_diag;
+            fp.psi = a.psi;
+            fp.lam = a.lam;
+            fp.state_stride = pb->dim;
+            fp.partial = a.partial;
+            QQ_HIP(launch_fast_pass(pp.fkind, sd.high != 0, pb->diag_type, fp, stream));
+        } else {
+            QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
+        }
+        if (g_prof) {
+            QQ_HIP(hipEventRecord(rec.stop, stream));
+            rec.meta.kind = pp.nstates > 1 ? 2 : 1;
+            rec.meta.pass_kind = (use_fast && pp.fkind >= 0) ? pp.fkind : -1;
+            rec.meta.high = sd.high;
+            rec.meta.full = !sd.high || sd.active == 0x0ff0;
+            rec.meta.diag_bytes = diag_bytes_of(pb->diag_type);
+            rec.meta.c128 = c128;
+            rec.meta.n = pb->n;
+            rec.meta.batch = B;
+            rec.meta.bytes = pass_bytes(pb, pp, B, c128);
+            g_prof_log.push_back(rec);
+        }
         slot_base += a.nslots;
     }
     FinalizeArgs fa;
@@ -431,7 +536,23 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
     int s = 0;
     for (const auto &pp : plan.passes)
         for (int o : pp.slot_out) fa.slot_out[s++] = (uint16_t)o;
+    ProfRec rec{};
+    if (g_prof) {
+        QQ_HIP(hipEventCreate(&rec.start));
+        QQ_HIP(hipEventCreate(&rec.stop));
+        QQ_HIP(hipEventRecord(rec.start, stream));
+    }
     QQ_HIP(launch_finalize(fa, stream));
+    if (g_prof) {
+        QQ_HIP(hipEventRecord(rec.stop, stream));
+        rec.meta.kind = 3;
+        rec.meta.pass_kind = -1;
+        rec.meta.c128 = c128;
+        rec.meta.n = pb->n;
+        rec.meta.batch = B;
+        rec.meta.bytes = (double)plan.nslots * B * L.G * sizeof(double);
+        g_prof_log.push_back(rec);
+    }
     return QQ_OK;
 }
 
@@ -482,6 +603,7 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
                             qq_problem **out)
 {
     g_err.clear();
+    if (const char *e = std::getenv("QQ_GENERIC_PASSES")) g_force_generic = e[0] == '1';
     if (!out) return fail(QQ_E_INVALID, "out is NULL");
     if (n < 1 || n > QQ_MAX_N) return fail(QQ_E_INVALID, "n = %d outside [1, %d]", n, QQ_MAX_N);
     if (!H) return fail(QQ_E_INVALID, "H is NULL");
@@ -831,7 +953,7 @@ static qq_status state_into(qq_problem *pb, int p, const double *params, int fla
     if (!params) return fail(QQ_E_INVALID, "params is NULL");
     if (!(flags & QQ_PARAMS_ON_DEVICE))
         if (qq_status st = check_params_host(params, 2 * (size_t)p); st != QQ_OK) return st;
-    const int f = flags & ~QQ_GRAD;
+    const int f = (flags & ~QQ_GRAD) | QQ_ENERGY;
     const Plan plan = make_plan(pb->n, p, plan_mode(f, true));
     L = make_layout(pb, p, 1, f, plan);
     QQ_HIP(hipSetDevice(pb->device));
@@ -909,6 +1031,32 @@ qq_status qq_topk(qq_problem *pb, int p, const double *params, int flags, int k,
     std::copy(hp.begin(), hp.end(), prob_out);
     if (cost_out) std::copy(hc.begin(), hc.end(), cost_out);
     return QQ_OK;
+}
+
+qq_status qq_profile_enable(int enable)
+{
+    g_prof = enable != 0;
+    return QQ_OK;
+}
+
+qq_status qq_profile_read(qq_launch_record *out, int max, int *count)
+{
+    if (!count || (max > 0 && !out)) return fail(QQ_E_INVALID, "NULL argument");
+    int k = 0;
+    qq_status st = QQ_OK;
+    for (auto &r : g_prof_log) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+            st = fail(QQ_E_DEVICE, "event timing failed");
+        r.meta.ms = ms;
+        if (k < max) out[k] = r.meta;
+        ++k;
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    g_prof_log.clear();
+    *count = std::min(k, std::max(max, 0));
+    return st;
 }
 
 qq_status qq_evaluate_plain(qq_problem *pb, int p, const double *params, int flags, void *stream_, double *energy_out,

@@ -15,7 +15,8 @@ namespace qq {
 // (4 waves), 16 amplitudes per thread and state.  Tile-local bit j maps to a
 // global qubit: bits 0..3 always map to qubits 0..3 (a 16-amplitude, 128-byte
 // contiguous run for complex64); bits 4..11 map either to qubits 4..11 (the
-// "low" tile, fully contiguous) or to qubits pos4..pos4+7 (a "high" tile).
+// "low" tile, fully contiguous) or to two runs of four qubits, pos4..pos4+3 and
+// pos8..pos8+3 (a "high" tile).
 // The 12 tile bits form three 4-bit register groups; a group is mixed in
 // registers after an LDS transpose brings it into the per-thread register index.
 constexpr int kTileBits = 12;
@@ -78,9 +79,9 @@ struct PassArgs {
     int G;            // workgroups per state
     uint64_t tiles;   // tiles per state
     uint64_t dim_mask;
-    int pos4, pos8;   // global positions of tile bits 4 and 8
-    int high;         // 0: tile bits are qubits 0..11, 1: qubits 0..3 and pos4..pos4+7
-    int hshift;       // high tile: number of tile-index bits placed at qubits 4..pos4-1
+    int pos4, pos8;   // qubits of tile bits 4..7 (pos4..pos4+3) and 8..11 (pos8..pos8+3), pos4 + 4 <= pos8
+    int high;         // 0: tile bits are qubits 0..11 (pos4 = 4, pos8 = 8)
+    int w1, w2;       // tile-index bits below pos4 (above qubit 3) and between the runs
     uint32_t flags;
     int nops;
     int nslots;
@@ -127,6 +128,23 @@ hipError_t launch_local_tables(int n, int diag_type, const PartDesc *d_pd, const
                                const int32_t *d_ell_i, int npairs, const int32_t *d_pair_ij, const double *d_pair_b,
                                const int32_t *d_pair_bi, const int32_t *d_qpu, double c0, int32_t c0_i, void *d_tables,
                                uint64_t total, hipStream_t s);
+
+// Specialised complex64 pass kernels (qq_fast.hip): one kernel per pass kind.
+enum FastPassKind : int { FK_FIRST = 0, FK_MID, FK_TURN, FK_LAST, FK_LASTG, FK_BMID, FK_BTURN, FK_BLAST };
+struct FastPassParams {
+    int B, G, p, k;
+    uint64_t tiles, dim_mask;
+    int pos4, pos8, w1, w2, active, store_psi;
+    int slot_base, slot_stride;
+    double amp0;
+    const double *params;
+    const void *diag;
+    void *psi;
+    void *lam;
+    uint64_t state_stride;
+    double *partial;
+};
+hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
 
 // Plain complex128 per-gate path (qq_plain.hip).
 struct PlainArgs {

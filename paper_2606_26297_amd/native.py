@@ -47,6 +47,12 @@ class QQError(RuntimeError):
         self.status = status
 
 
+class QQLaunchRecord(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("pass_kind", ctypes.c_int), ("high", ctypes.c_int),
+                ("full", ctypes.c_int), ("diag_bytes", ctypes.c_int), ("c128", ctypes.c_int), ("n", ctypes.c_int), ("batch", ctypes.c_int),
+                ("bytes", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
 class QQInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("is_integer", ctypes.c_int), ("diag_bytes", ctypes.c_int),
                 ("num_qpus", ctypes.c_int), ("c0", ctypes.c_double), ("alpha", ctypes.c_double),
@@ -79,6 +85,8 @@ SIGNATURES = {
     "qq_probabilities": ([_vp, _int, _vp, _int, _vp, _vp], _int),
     "qq_topk": ([_vp, _int, _vp, _int, _int, _u64p, _dp, _dp, _vp], _int),
     "qq_evaluate_plain": ([_vp, _int, _dp, _int, _vp, _dp, _dp], _int),
+    "qq_profile_enable": ([_int], _int),
+    "qq_profile_read": ([ctypes.c_void_p, _int, ctypes.POINTER(_int)], _int),
 }
 
 _LIB = None
@@ -252,3 +260,32 @@ def qq_evaluate_plain(handle, p, params, flags, stream=None):
     g = np.zeros(2 * p)
     _check(lib().qq_evaluate_plain(handle, int(p), _ptr(x), int(flags), _stream_ptr(stream), _ptr(e), _ptr(g)))
     return float(e[0]), g
+
+
+def qq_profile_enable(enable: bool):
+    _check(lib().qq_profile_enable(1 if enable else 0))
+
+
+def qq_profile_read(max_records: int = 1 << 16):
+    """List of dicts {kind, c128, n, batch, bytes, ms} of the launches recorded since the last read."""
+    buf = (QQLaunchRecord * max_records)()
+    cnt = _int(0)
+    _check(lib().qq_profile_read(ctypes.cast(buf, ctypes.c_void_p), max_records, ctypes.byref(cnt)))
+    return [{"kind": r.kind, "pass_kind": r.pass_kind, "high": r.high, "full": r.full, "diag_bytes": r.diag_bytes,
+             "c128": r.c128, "n": r.n, "batch": r.batch, "bytes": r.bytes, "ms": r.ms} for r in buf[:cnt.value]]
+
+
+PASS_KIND_NAMES = ["FK_FIRST", "FK_MID", "FK_TURN", "FK_LAST", "FK_LASTG", "FK_BMID", "FK_BTURN", "FK_BLAST"]
+DIAG_TYPE_NAMES = {8: "double", 4: "int", 2: "short"}
+
+
+def kernel_name(rec) -> str:
+    """The kernel instantiation a launch record belongs to, in rocprofv3's naming."""
+    if rec["kind"] == 3:
+        return "finalize_kernel"
+    dt = DIAG_TYPE_NAMES[rec["diag_bytes"]]
+    if rec["pass_kind"] >= 0:
+        tf = lambda x: "true" if x else "false"  # noqa: E731
+        return f"fast_pass<{rec['pass_kind']}, {tf(rec['high'])}, {tf(rec['full'])}, {dt}>"
+    real = "double" if rec["c128"] else "float"
+    return f"pass_kernel<{real}, {2 if rec['kind'] == 2 else 1}, {dt}>"

@@ -1,0 +1,129 @@
+"""Full-size (n = 28) GPU checks in the benchmark's launch configuration (16 states per call).
+
+The FP64 oracle cannot evaluate n = 28 one output at a time in test time, so
+these checks use results that hold at any size:
+  * separable instances (no couplings): the state is a product of single-qubit
+    states, so E = c0 + sum_i l_i P_i(1) with each P_i from a 2x2 evolution, and
+    the gradient follows from central differences of that closed form;
+  * cluster-product instances (couplings only inside blocks of 7 qubits):
+    E = c0 + sum_m E_m and grad = sum_m grad_m with each block solved by the oracle.
+The blocks straddle every qubit-set boundary of the n = 28 pass plan
+(sets {0..11}, {12..15, 24..27}, {16..23}).
+Tolerance: 1e-5 relative for complex64 (energy |dE| / max(|E|, sigma_C),
+gradient ||dg||_inf / ||g||_inf), 1e-10 for complex128.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_26297_amd import workloads as W
+from paper_2606_26297_amd.qaoa import Problem
+
+pytestmark = pytest.mark.gpu
+
+N = 28
+WAVE = 16
+
+
+def p1_qubit(ell, x):
+    v = np.array([1, 1], dtype=complex) / np.sqrt(2)
+    for k in range(len(x) // 2):
+        g, b = x[2 * k], x[2 * k + 1]
+        v = np.array([1, np.exp(-1j * g * ell)]) * v
+        v = np.array([[np.cos(b), -1j * np.sin(b)], [-1j * np.sin(b), np.cos(b)]]) @ v
+    return abs(v[1]) ** 2
+
+
+def separable_energy(ell, c0, x):
+    return c0 + sum(li * p1_qubit(li, x) for li in ell)
+
+
+def separable_grad(ell, c0, x, h=1e-6):
+    g = np.empty_like(x)
+    for j in range(len(x)):
+        xp, xm = x.copy(), x.copy()
+        xp[j] += h
+        xm[j] -= h
+        g[j] = (separable_energy(ell, c0, xp) - separable_energy(ell, c0, xm)) / (2 * h)
+    return g
+
+
+def rel_e(e, eref, sigma):
+    return np.max(np.abs(e - eref) / np.maximum(np.abs(eref), sigma))
+
+
+def rel_g(g, gref):
+    return max(np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(g, gref))
+
+
+@pytest.fixture(scope="module")
+def sep_problem():
+    inst = W.separable(N, 41, scale=0.5)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    ell, _ = O.canonicalise(inst.H, inst.f)
+    return inst, pb, ell
+
+
+@pytest.mark.parametrize("c128", [False, True])
+def test_separable_n28_energy_and_gradient(sep_problem, c128):
+    inst, pb, ell = sep_problem
+    p = 3
+    B = 4 if c128 else WAVE
+    x = W.random_params(p, B, 42)
+    e, g = pb.evaluate(x, grad=True, c128=c128)
+    ke = min(B, 4)
+    eref = np.array([separable_energy(ell, inst.c0, xb) for xb in x[:ke]])
+    gref = np.array([separable_grad(ell, inst.c0, xb) for xb in x[:ke]])
+    tol_e, tol_g = (1e-10, 1e-8) if c128 else (1e-5, 1e-5)
+    sigma = pb.info.sigma_c
+    assert rel_e(e[:ke], eref, sigma) <= tol_e
+    assert rel_g(g[:ke], gref) <= tol_g  # FD of the closed form is accurate to ~1e-9
+
+
+@pytest.fixture(scope="module")
+def cluster_problem():
+    inst = W.cluster_product([7, 7, 7, 7], 43)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    return inst, pb
+
+
+@pytest.mark.parametrize("c128", [False, True])
+def test_cluster_product_n28_energy_and_gradient(cluster_problem, c128):
+    inst, pb = cluster_problem
+    p = 4
+    B = 2 if c128 else WAVE
+    x = W.random_params(p, B, 44)
+    e, g = pb.evaluate(x, grad=True, c128=c128)
+    ks = min(B, 3)
+    eref = np.full(ks, inst.c0)
+    gref = np.zeros((ks, 2 * p))
+    for off, m in inst.meta["blocks"]:
+        d = O.cost_diagonal(inst.H[off:off + m, off:off + m], None, 0.0)
+        for b in range(ks):
+            eb, gb = O.gradient(d, x[b])
+            eref[b] += eb
+            gref[b] += gb
+    tol = 1e-10 if c128 else 1e-5
+    assert rel_e(e[:ks], eref, pb.info.sigma_c) <= tol
+    assert rel_g(g[:ks], gref) <= tol
+
+
+def test_workload_n28_complex64_vs_complex128_and_fd():
+    """The benchmark instance: specialised complex64 kernels against the generic complex128
+    kernel, and the complex128 gradient against central differences of complex128 energies."""
+    inst, x = W.workload3(batch=WAVE, p=8)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    e64, g64 = pb.evaluate(x, grad=True)
+    e128, g128 = pb.evaluate(x[:2], grad=True, c128=True)
+    sigma = pb.info.sigma_c
+    assert rel_e(e64[:2], e128, sigma) <= 1e-5
+    assert rel_g(g64[:2], g128) <= 1e-5
+    h = 1e-6
+    js = [0, 5, 15]  # gamma_1, beta_3, beta_8
+    xp = np.repeat(x[:1], len(js), axis=0)
+    xm = xp.copy()
+    for r, j in enumerate(js):
+        xp[r, j] += h
+        xm[r, j] -= h
+    fd = (pb.evaluate(xp, c128=True) - pb.evaluate(xm, c128=True)) / (2 * h)
+    assert np.max(np.abs(fd - g128[0, js])) <= 1e-6 * np.max(np.abs(g128[0]))
