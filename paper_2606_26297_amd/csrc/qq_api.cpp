@@ -410,13 +410,13 @@ qq_status check_device_fits(int device, size_t bytes, const char *what)
     return QQ_OK;
 }
 
-// Algorithmic HBM bytes of one pass: every state load and store, plus one
-// cost-diagonal read per operation that needs C(z) (per state; the
+// Algorithmic HBM bytes of one pass: every state load and store (per state),
+// plus one cost-diagonal read per operation that needs C(z) -- counted once per
+// launch, since every state of the batch reads the same diagonal entries (the
 // partitioned phase also reads the cross-QPU diagonal).
 double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128)
 {
     const double es = c128 ? 16.0 : 8.0, d = diag_bytes_of(pb->diag_type);
-    const double amps = (double)pb->dim * B;
     int moves = 0;
     if (pp.flags & PF_LOAD_PSI) ++moves;
     if (pp.flags & PF_LOAD_LAM) ++moves;
@@ -428,7 +428,7 @@ double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128)
         if ((o.kind == OP_PHASE || (o.kind == OP_GGAMMA && (o.flags & OPF_UNPHASE))) && (o.flags & OPF_PARTITIONED))
             diag_reads += 1;
     }
-    return amps * (moves * es + diag_reads * d);
+    return (double)pb->dim * (B * moves * es + diag_reads * d);
 }
 
 // Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.

@@ -47,6 +47,20 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t tile, int a, int c, int w
     return (lo << 4) | (mid << (a + 4)) | (tile << (c + 4));
 }
 
+// (state b, workgroup slot g) of this workgroup, XCD-aware.  Workgroups are
+// dispatched round-robin over the 8 XCDs (block i runs on XCD i mod 8), each XCD
+// with its own L2.  Renumbering so that the B workgroups sharing a tile index
+// (all states of the batch, which read the same cost-diagonal entries) are
+// consecutive on one XCD lets that L2 serve the diagonal to all of them.
+__device__ __forceinline__ void block_coords(int B, int G, int &b, int &g)
+{
+    const uint32_t nb = (uint32_t)B * (uint32_t)G, i = blockIdx.x;
+    uint32_t L = i;
+    if ((nb & 7u) == 0) L = (i & 7u) * (nb >> 3) + (i >> 3);
+    b = (int)(L % (uint32_t)B);
+    g = (int)(L / (uint32_t)B);
+}
+
 // Wave-uniform 64-bit value (kept in scalar registers and opaque to loop-invariant hoisting).
 __device__ __forceinline__ uint64_t uni64(uint64_t x)
 {

@@ -460,8 +460,8 @@ fast_pass(const FastArgs a)
     __shared__ double s_red[kThreads / 64][4];
 
     const int t = threadIdx.x;
-    const int b = blockIdx.x % a.B;
-    const int g = blockIdx.x / a.B;
+    int b, g;
+    block_coords(a.B, a.G, b, g);
     const double *x = a.params + (size_t)b * 2 * a.p;
 
     // layer constants (uniform)

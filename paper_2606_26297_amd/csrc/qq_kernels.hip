@@ -36,8 +36,8 @@ __global__ void __launch_bounds__(kThreads) pass_kernel(const PassArgs a)
 
     const int t = threadIdx.x;
     for (int k = t; k < kMaxImmSlots; k += kThreads) s_imm[k] = 0.0;
-    const int b = blockIdx.x % a.B;
-    const int g = blockIdx.x / a.B;
+    int b, g;
+    block_coords(a.B, a.G, b, g);
     {
         const double *x = a.params + (size_t)b * 2 * a.p;
         if (t < a.p) {
