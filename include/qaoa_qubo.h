@@ -187,6 +187,48 @@ qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int 
                   double *prob_out, double *cost_out, void *stream);
 
 /*
+ * Many problems of uneven n and p in one persistent launch (runtime
+ * optimisation section, throughput subsection: independent evaluations run
+ * together instead of one request each).
+ *
+ * Problem i evaluates batch[i] parameter sets of depth p[i] (params[i]:
+ * batch[i] x 2p[i] interleaved doubles, host memory unless
+ * QQ_PARAMS_ON_DEVICE) into energy_out[i] (batch[i] doubles) and, with
+ * QQ_GRAD, grad_out[i] (batch[i] x 2p[i]); host memory unless
+ * QQ_OUT_ON_DEVICE.  Same results as qq_evaluate on each problem, up to the
+ * order of the FP64 partial sums (complex64 state, FP64 diagonal, phase
+ * reduction and accumulators).
+ *
+ * Execution: one launch per cost-diagonal element type present (at most
+ * three) drains a queue of (problem, parameter set, pass, tile chunk) items in
+ * level-major order from an atomic ticket; a problem with n <= 12 is one item
+ * per parameter set.  Items of a pass wait, bounded in time, for the previous
+ * pass on the same state; a wait longer than opt->wait_limit_ms sets a device
+ * flag, the launch drains early and the call returns QQ_E_DEVICE.  The call
+ * synchronises the stream before returning (it reads that flag).
+ *
+ * Limits: every problem on one device, n <= 31, 1 <= p <= QQ_MAX_P,
+ * batch >= 1.  QQ_C128 and QQ_PARTITIONED are not served here
+ * (QQ_E_UNSUPPORTED; use qq_evaluate).
+ * workspace: device buffer of ws_bytes >= qq_workspace_size_many(), or NULL
+ * to let the library allocate one for this call.  opt may be NULL (defaults).
+ * Errors: QQ_E_INVALID, QQ_E_UNSUPPORTED, QQ_E_WORKSPACE, QQ_E_TOO_LARGE,
+ * QQ_E_NOMEM, QQ_E_DEVICE.
+ */
+typedef struct {
+    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: automatic */
+    int max_workgroups;    /* cap on the persistent grid; 0: every workgroup that fits on the device at once */
+    double wait_limit_ms;  /* bound on one dependency wait; 0: 2000 ms */
+} qq_many_options;
+
+qq_status qq_workspace_size_many(int count, qq_problem *const *problems, const int *p, const int *batch, int flags,
+                                 const qq_many_options *opt, size_t *bytes);
+
+qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p, const int *batch,
+                           const double *const *params, int flags, const qq_many_options *opt, void *workspace,
+                           size_t ws_bytes, void *stream, double *const *energy_out, double *const *grad_out);
+
+/*
  * Measurement baseline: the plain complex128 form with one kernel per gate
  * (one phase kernel per layer, one RX kernel per qubit and layer, an energy
  * reduction, and the same adjoint equations unfused), one parameter set per
@@ -206,7 +248,8 @@ qq_status qq_evaluate_plain(qq_problem *prob, int p, const double *params, int f
  * Profiling is process-wide and off by default; it is not thread-safe.
  */
 typedef struct {
-    int kind;       /* 1: forward pass (one state), 2: adjoint pass (psi and lambda), 3: final reduction */
+    int kind;       /* 1: forward pass (one state), 2: adjoint pass (psi and lambda), 3: final reduction,
+                       4: persistent many-problem launch */
     int pass_kind;  /* complex64 specialised kernel: 0 first, 1 mid, 2 turn, 3 last, 4 last+adjoint seed,
                        5 adjoint mid, 6 adjoint turn, 7 adjoint last; -1: generic pass kernel */
     int high;       /* 1 when the pass mixes qubits above 11 (strided tile) */

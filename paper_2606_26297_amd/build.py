@@ -16,7 +16,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["qq_kernels.hip", "qq_fast.hip", "qq_plain.hip"]
+HIP_SOURCES = ["qq_kernels.hip", "qq_fast.hip", "qq_many.hip", "qq_plain.hip"]
 CPP_SOURCES = ["qq_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
@@ -45,7 +45,7 @@ def build(verbose: bool = False, resource_usage: bool = False) -> str:
     for src in CPP_SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
         jobs.append([HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj])
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(jobs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(jobs))) as ex:
         outs = list(ex.map(lambda c: _run(c, verbose), jobs))
     if resource_usage:
         for o in outs:

@@ -581,6 +581,211 @@ qq_status eval_core(qq_problem *pb, int p, int batch, const double *params, int 
     return run_plan(pb, plan, L, p, batch, flags, ws, d_params, stream);
 }
 
+// ---- many problems in one persistent launch -----------------------------------------------
+// One launch per cost-diagonal element type present (the kernel is specialised on it).
+struct ManyGroup {
+    int diag_type = DIAG_F64;
+    std::vector<int> members;  // problem indices, in queue priority order
+    std::vector<ManyInst> inst;
+    std::vector<ManyPass> pass;
+    std::vector<ManySeg> seg;
+    std::vector<uint16_t> slot_out;
+    uint32_t total = 0;
+    int nstates = 0;
+    size_t partial_doubles = 0;
+    size_t state_bytes = 0;
+    double bytes = 0;  // algorithmic HBM bytes of the launch
+    // workspace offsets
+    size_t ctl = 0, desc = 0, partial = 0, states = 0;
+    size_t inst_off = 0, pass_off = 0, seg_off = 0, slot_off = 0, desc_bytes = 0;
+};
+
+struct ManyLayout {
+    std::vector<ManyGroup> groups;
+    std::vector<size_t> param_off, out_off;  // doubles, per problem
+    size_t params = 0, out = 0, total = 0;
+};
+
+constexpr double kDefaultWaitMs = 2000.0;
+
+int many_tiles_per_chunk(uint64_t tiles, const qq_many_options *opt)
+{
+    if (opt && opt->tiles_per_chunk > 0) return (int)std::min<uint64_t>((uint64_t)opt->tiles_per_chunk, tiles);
+    // about 256 chunks per pass: enough items per level to fill the device, few enough
+    // that per-item overhead stays small
+    return (int)std::max<uint64_t>(1, tiles / 256);
+}
+
+qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *batch, int flags,
+                    const qq_many_options *opt, ManyLayout &M)
+{
+    const bool grad = flags & QQ_GRAD;
+    const int mode = plan_mode(flags | QQ_ENERGY, false);
+    // problem order inside each level: longest pass chain first, then most tiles
+    std::vector<int> order(count);
+    std::vector<Plan> plans(count);
+    for (int i = 0; i < count; ++i) {
+        order[i] = i;
+        plans[i] = make_plan(pbs[i]->n, p[i], mode);
+        if (plans[i].nslots > kMaxSlots)
+            return fail(QQ_E_UNSUPPORTED, "problem %d: plan needs %d accumulator slots (max %d)", i, plans[i].nslots,
+                        kMaxSlots);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const size_t pa = plans[a].passes.size(), pb = plans[b].passes.size();
+        if (pa != pb) return pa > pb;
+        return pbs[a]->n > pbs[b]->n;
+    });
+    const int types[3] = {DIAG_F64, DIAG_I32, DIAG_I16};
+    M.param_off.assign(count, 0);
+    M.out_off.assign(count, 0);
+    size_t poff = 0, ooff = 0;
+    for (int i = 0; i < count; ++i) {
+        M.param_off[i] = poff;
+        poff += (size_t)batch[i] * 2 * p[i];
+        M.out_off[i] = ooff;
+        ooff += (size_t)batch[i] * (1 + 2 * p[i]);
+    }
+    size_t off = 0;
+    M.params = off;
+    off += align_up(poff * sizeof(double));
+    M.out = off;
+    off += align_up(ooff * sizeof(double));
+    for (int dt : types) {
+        ManyGroup G;
+        G.diag_type = dt;
+        for (int i : order)
+            if (pbs[i]->diag_type == dt) G.members.push_back(i);
+        if (G.members.empty()) continue;
+        size_t state_off = 0;
+        for (int i : G.members) {
+            const qq_problem *pb = pbs[i];
+            const Plan &plan = plans[i];
+            ManyInst I;
+            std::memset(&I, 0, sizeof I);
+            I.n = pb->n;
+            I.p = p[i];
+            I.B = batch[i];
+            I.tiles = tiles_per_state(pb->n);
+            I.dim_mask = pb->dim - 1;
+            I.amp0 = 1.0 / std::sqrt((double)pb->dim);
+            I.escale = pb->n < kTileBits ? std::ldexp(1.0, pb->n - kTileBits) : 1.0;
+            I.state0 = G.nstates;
+            G.nstates += I.B;
+            I.pass_off = (int)G.pass.size();
+            I.slot_off = (int)G.slot_out.size();
+            I.partial_off = G.partial_doubles;
+            if (plan.sets.size() == 1) {
+                // the whole evaluation in one item per parameter set; slot o is output o
+                ManyPass P;
+                std::memset(&P, 0, sizeof P);
+                P.kind = FK_SINGLE;
+                P.active = plan.sets[0].active;
+                P.nact = __builtin_popcount(P.active);
+                P.nslots = grad ? 1 + 2 * I.p : 1;
+                G.pass.push_back(P);
+                I.npasses = 1;
+                I.nchunks = 1;
+                I.tpc = 1;
+                I.nslots = P.nslots;
+                for (int o = 0; o < I.nslots; ++o) G.slot_out.push_back((uint16_t)o);
+                G.bytes += (double)pb->dim * diag_bytes_of(pb->diag_type);
+            } else {
+                I.tpc = many_tiles_per_chunk(I.tiles, opt);
+                I.nchunks = (int)((I.tiles + (uint64_t)I.tpc - 1) / (uint64_t)I.tpc);
+                I.npasses = (int)plan.passes.size();
+                int slot_base = 0;
+                for (const PassPlan &pp : plan.passes) {
+                    const SetDesc &sd = plan.sets[pp.set];
+                    ManyPass P;
+                    std::memset(&P, 0, sizeof P);
+                    P.kind = pp.fkind;
+                    P.k = pp.fk;
+                    P.geom = !sd.high ? 0 : (sd.active == 0x0ff0 ? 1 : 2);
+                    P.pos4 = sd.pos4;
+                    P.pos8 = sd.pos8;
+                    P.w1 = sd.pos4 - 4;
+                    P.w2 = sd.pos8 - sd.pos4 - 4;
+                    P.active = sd.active;
+                    P.nact = __builtin_popcount(sd.active);
+                    P.store_psi = (pp.flags & PF_STORE_PSI) ? 1 : 0;
+                    P.slot_base = slot_base;
+                    P.nslots = (int)pp.slot_out.size();
+                    slot_base += P.nslots;
+                    for (int o : pp.slot_out) G.slot_out.push_back((uint16_t)o);
+                    G.pass.push_back(P);
+                    G.bytes += pass_bytes(pb, pp, I.B, false);
+                }
+                I.nslots = slot_base;
+                const size_t sb = (size_t)pb->dim * sizeof(float2) * I.B;
+                I.psi = reinterpret_cast<void *>(state_off);  // relative; fixed up below
+                state_off += align_up(sb);
+                if (grad) {
+                    I.lam = reinterpret_cast<void *>(state_off);
+                    state_off += align_up(sb);
+                }
+            }
+            G.partial_doubles += (size_t)I.nslots * I.B * I.nchunks;
+            G.inst.push_back(I);
+        }
+        G.state_bytes = state_off;
+        // level-major segments
+        int max_passes = 0;
+        for (const ManyInst &I : G.inst) max_passes = std::max(max_passes, I.npasses);
+        uint64_t ticket = 0;
+        for (int j = 0; j < max_passes; ++j)
+            for (size_t k = 0; k < G.inst.size(); ++k) {
+                const ManyInst &I = G.inst[k];
+                if (j >= I.npasses) continue;
+                for (int b = 0; b < I.B; ++b) {
+                    G.seg.push_back({(uint32_t)ticket, (uint32_t)k, (uint32_t)b, (uint32_t)j});
+                    ticket += (uint64_t)I.nchunks;
+                }
+            }
+        if (ticket >= 0xffffffffull) return fail(QQ_E_TOO_LARGE, "%llu work items exceed 2^32", (unsigned long long)ticket);
+        G.total = (uint32_t)ticket;
+        // workspace regions of the group
+        G.ctl = off;
+        off += align_up((size_t)(2 + G.nstates) * sizeof(uint32_t));
+        G.inst_off = 0;
+        G.pass_off = align_up(G.inst.size() * sizeof(ManyInst), 16);
+        G.seg_off = G.pass_off + align_up(G.pass.size() * sizeof(ManyPass), 16);
+        G.slot_off = G.seg_off + align_up(G.seg.size() * sizeof(ManySeg), 16);
+        G.desc_bytes = G.slot_off + G.slot_out.size() * sizeof(uint16_t);
+        G.desc = off;
+        off += align_up(G.desc_bytes);
+        G.partial = off;
+        off += align_up(std::max<size_t>(1, G.partial_doubles) * sizeof(double));
+        G.states = off;
+        off += align_up(G.state_bytes);
+        M.groups.push_back(std::move(G));
+    }
+    M.total = off;
+    return QQ_OK;
+}
+
+qq_status validate_many(int count, qq_problem *const *pbs, const int *p, const int *batch, int flags)
+{
+    if (count < 1) return fail(QQ_E_INVALID, "count = %d must be >= 1", count);
+    if (!pbs || !p || !batch) return fail(QQ_E_INVALID, "problems / p / batch is NULL");
+    const int known = QQ_ENERGY | QQ_GRAD | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE;
+    if (flags & (QQ_C128 | QQ_PARTITIONED))
+        return fail(QQ_E_UNSUPPORTED, "qq_evaluate_many runs complex64 monolithic evaluations only "
+                                      "(use qq_evaluate for QQ_C128 / QQ_PARTITIONED)");
+    if (flags & ~known) return fail(QQ_E_INVALID, "unknown flag bits 0x%x", flags & ~known);
+    for (int i = 0; i < count; ++i) {
+        if (!pbs[i]) return fail(QQ_E_INVALID, "problems[%d] is NULL", i);
+        if (pbs[i]->device != pbs[0]->device)
+            return fail(QQ_E_INVALID, "problems[%d] is on device %d, problems[0] on %d", i, pbs[i]->device,
+                        pbs[0]->device);
+        if (pbs[i]->n > kFastMaxN)
+            return fail(QQ_E_UNSUPPORTED, "problems[%d]: n = %d above %d (use qq_evaluate)", i, pbs[i]->n, kFastMaxN);
+        if (p[i] < 1 || p[i] > QQ_MAX_P) return fail(QQ_E_INVALID, "p[%d] = %d outside [1, %d]", i, p[i], QQ_MAX_P);
+        if (batch[i] < 1) return fail(QQ_E_INVALID, "batch[%d] = %d must be >= 1", i, batch[i]);
+    }
+    return QQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1030,6 +1235,156 @@ qq_status qq_topk(qq_problem *pb, int p, const double *params, int flags, int k,
     std::copy(hi.begin(), hi.end(), idx_out);
     std::copy(hp.begin(), hp.end(), prob_out);
     if (cost_out) std::copy(hc.begin(), hc.end(), cost_out);
+    return QQ_OK;
+}
+
+qq_status qq_workspace_size_many(int count, qq_problem *const *problems, const int *p, const int *batch, int flags,
+                                 const qq_many_options *opt, size_t *bytes)
+{
+    g_err.clear();
+    if (!bytes) return fail(QQ_E_INVALID, "bytes is NULL");
+    if (qq_status st = validate_many(count, problems, p, batch, flags); st != QQ_OK) return st;
+    ManyLayout M;
+    if (qq_status st = plan_many(count, problems, p, batch, flags, opt, M); st != QQ_OK) return st;
+    *bytes = M.total;
+    return QQ_OK;
+}
+
+qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p, const int *batch,
+                           const double *const *params, int flags, const qq_many_options *opt, void *workspace,
+                           size_t ws_bytes, void *stream_, double *const *energy_out, double *const *grad_out)
+{
+    g_err.clear();
+    if (qq_status st = validate_many(count, problems, p, batch, flags); st != QQ_OK) return st;
+    const bool grad = flags & QQ_GRAD;
+    if (!params || !energy_out || (grad && !grad_out)) return fail(QQ_E_INVALID, "params / energy_out / grad_out is NULL");
+    for (int i = 0; i < count; ++i) {
+        if (!params[i]) return fail(QQ_E_INVALID, "params[%d] is NULL", i);
+        if (!energy_out[i]) return fail(QQ_E_INVALID, "energy_out[%d] is NULL", i);
+        if (grad && !grad_out[i]) return fail(QQ_E_INVALID, "grad_out[%d] is NULL", i);
+        if (!(flags & QQ_PARAMS_ON_DEVICE))
+            if (qq_status st = check_params_host(params[i], (size_t)batch[i] * 2 * p[i]); st != QQ_OK) return st;
+    }
+    if (opt && (opt->tiles_per_chunk < 0 || opt->max_workgroups < 0 || !(opt->wait_limit_ms >= 0.0)))
+        return fail(QQ_E_INVALID, "negative or non-finite option");
+    ManyLayout M;
+    if (qq_status st = plan_many(count, problems, p, batch, flags, opt, M); st != QQ_OK) return st;
+    const int device = problems[0]->device;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(device));
+    DevBuf own;
+    char *ws = static_cast<char *>(workspace);
+    if (!ws) {
+        if (qq_status st = check_device_fits(device, M.total, "the workspace"); st != QQ_OK) return st;
+        if (hipMalloc(&own.p, M.total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) for the workspace failed", M.total);
+        ws = static_cast<char *>(own.p);
+    } else if (ws_bytes < M.total) {
+        return fail(QQ_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, M.total);
+    }
+    int rate_khz = 0;
+    QQ_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device));
+    const double wait_ms = (opt && opt->wait_limit_ms > 0.0) ? opt->wait_limit_ms : kDefaultWaitMs;
+    const uint64_t spin_ticks = (uint64_t)(wait_ms * std::max(1, rate_khz));
+
+    // host staging: packed parameters, then each group's descriptors (device addresses fixed up)
+    std::vector<char> stage;
+    const size_t nparam = M.out - M.params;
+    if (!(flags & QQ_PARAMS_ON_DEVICE)) {
+        stage.resize(nparam);
+        for (int i = 0; i < count; ++i)
+            std::memcpy(stage.data() + M.param_off[i] * sizeof(double), params[i],
+                        (size_t)batch[i] * 2 * p[i] * sizeof(double));
+        QQ_HIP(hipMemcpyAsync(ws + M.params, stage.data(), nparam, hipMemcpyHostToDevice, stream));
+    }
+    std::vector<std::vector<char>> blobs(M.groups.size());
+    for (size_t gi = 0; gi < M.groups.size(); ++gi) {
+        ManyGroup &G = M.groups[gi];
+        for (size_t k = 0; k < G.inst.size(); ++k) {
+            ManyInst &I = G.inst[k];
+            const int i = G.members[k];
+            I.params = (flags & QQ_PARAMS_ON_DEVICE) ? params[i]
+                                                     : reinterpret_cast<const double *>(ws + M.params) + M.param_off[i];
+            I.diag = problems[i]->d_diag;
+            if (I.npasses > 1 || G.pass[I.pass_off].kind != FK_SINGLE) {
+                I.psi = ws + G.states + reinterpret_cast<size_t>(I.psi);
+                I.lam = grad ? ws + G.states + reinterpret_cast<size_t>(I.lam) : nullptr;
+            }
+            if (flags & QQ_OUT_ON_DEVICE) {
+                I.energy_out = energy_out[i];
+                I.grad_out = grad ? grad_out[i] : nullptr;
+                I.out_ws = nullptr;
+            } else {
+                I.energy_out = nullptr;
+                I.grad_out = nullptr;
+                I.out_ws = reinterpret_cast<double *>(ws + M.out) + M.out_off[i];
+            }
+        }
+        std::vector<char> &blob = blobs[gi];
+        blob.assign(G.desc_bytes, 0);
+        std::memcpy(blob.data() + G.inst_off, G.inst.data(), G.inst.size() * sizeof(ManyInst));
+        std::memcpy(blob.data() + G.pass_off, G.pass.data(), G.pass.size() * sizeof(ManyPass));
+        std::memcpy(blob.data() + G.seg_off, G.seg.data(), G.seg.size() * sizeof(ManySeg));
+        std::memcpy(blob.data() + G.slot_off, G.slot_out.data(), G.slot_out.size() * sizeof(uint16_t));
+        QQ_HIP(hipMemcpyAsync(ws + G.desc, blob.data(), G.desc_bytes, hipMemcpyHostToDevice, stream));
+    }
+    for (ManyGroup &G : M.groups) {
+        QQ_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ws + G.ctl), 0u, (size_t)(2 + G.nstates), stream));
+        ManyArgs a;
+        a.inst = reinterpret_cast<const ManyInst *>(ws + G.desc + G.inst_off);
+        a.pass = reinterpret_cast<const ManyPass *>(ws + G.desc + G.pass_off);
+        a.seg = reinterpret_cast<const ManySeg *>(ws + G.desc + G.seg_off);
+        a.slot_out = reinterpret_cast<const uint16_t *>(ws + G.desc + G.slot_off);
+        a.nseg = (int)G.seg.size();
+        a.grad = grad ? 1 : 0;
+        a.total = G.total;
+        a.ctl = reinterpret_cast<uint32_t *>(ws + G.ctl);
+        a.partial = reinterpret_cast<double *>(ws + G.partial);
+        a.spin_ticks = spin_ticks;
+        ProfRec rec{};
+        if (g_prof) {
+            QQ_HIP(hipEventCreate(&rec.start));
+            QQ_HIP(hipEventCreate(&rec.stop));
+            QQ_HIP(hipEventRecord(rec.start, stream));
+        }
+        int grid = 0;
+        QQ_HIP(launch_many(a, G.diag_type, opt ? opt->max_workgroups : 0, stream, &grid));
+        if (g_prof) {
+            QQ_HIP(hipEventRecord(rec.stop, stream));
+            rec.meta.kind = 4;
+            rec.meta.pass_kind = -1;
+            rec.meta.diag_bytes = diag_bytes_of(G.diag_type);
+            rec.meta.n = 0;
+            rec.meta.batch = G.nstates;
+            rec.meta.bytes = G.bytes;
+            g_prof_log.push_back(rec);
+        }
+    }
+    // error flags (and host outputs)
+    std::vector<uint32_t> flags_h(M.groups.size(), 0);
+    for (size_t gi = 0; gi < M.groups.size(); ++gi)
+        QQ_HIP(hipMemcpyAsync(&flags_h[gi], ws + M.groups[gi].ctl + sizeof(uint32_t), sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, stream));
+    std::vector<double> h;
+    if (!(flags & QQ_OUT_ON_DEVICE)) {
+        size_t nout = 0;
+        for (int i = 0; i < count; ++i) nout += (size_t)batch[i] * (1 + 2 * p[i]);
+        h.resize(nout);
+        QQ_HIP(hipMemcpyAsync(h.data(), ws + M.out, nout * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    QQ_HIP(hipStreamSynchronize(stream));
+    for (uint32_t f : flags_h)
+        if (f) return fail(QQ_E_DEVICE, "persistent launch: a dependency wait exceeded %.0f ms; results are invalid", wait_ms);
+    if (!(flags & QQ_OUT_ON_DEVICE)) {
+        for (int i = 0; i < count; ++i) {
+            const size_t nout = 1 + 2 * (size_t)p[i];
+            const double *src = h.data() + M.out_off[i];
+            for (int b = 0; b < batch[i]; ++b) {
+                energy_out[i][b] = src[(size_t)b * nout];
+                if (grad)
+                    for (int j = 0; j < 2 * p[i]; ++j) grad_out[i][(size_t)b * 2 * p[i] + j] = src[(size_t)b * nout + 1 + j];
+            }
+        }
+    }
     return QQ_OK;
 }
 

@@ -1,455 +1,12 @@
-// qq_fast.hip -- complex64 pass kernels specialised per pass kind.
-//
-// Same computation as the generic pass kernel (a tile of 2^12 amplitudes per
-// workgroup, three 4-bit register groups rotated by LDS transposes), with
-// the operation sequence, the layouts and the qubit-set geometry fixed at
-// compile time so the register allocator sees one straight-line program.
-//
-// Mixer in factored form.  RX(2 beta) = cos(beta) I - i sin(beta) X is
-// applied as sigma * M with
-//     M = I - i t X,  t = tan(beta)        when |cos| >= |sin|   ("form A"),
-//     M = u I - i X,  u = cot(beta)        otherwise             ("form B"),
-// so each output component is one FMA.  t (or u) is rounded to float once and
-// sigma = +-1/sqrt(1 + t^2) is computed in FP64 from the rounded value, which
-// keeps sigma*M exactly unitary up to the final float rounding of
-// sigma^(number of mixed qubits), applied once per mixer operation.  The
-// inverse rotation flips the sign of t (form A) or of u and sigma (form B).
-//
-// d E / d beta_k = 2 Im sum_q <lambda|X_q|psi> is accumulated per register
-// group as sum_r Im(conj(lambda_r) * sum_{q in group} psi_{r xor q}): FP32
-// products over the 16 registers of a thread, added to FP64 accumulators.
-#include "qq_device.h"
+// qq_fast.hip -- complex64 pass kernels, one launch per pass, one kernel
+// instantiation per pass kind and qubit-set geometry (bodies in qq_passes.h).
+#include "qq_passes.h"
 
 namespace qq {
 namespace {
 
 using namespace dev;
-
-// exp(-i theta) for theta = gamma C: w = (gamma / 2 pi) C in FP64 (revolutions), reduced
-// to u = w - rint(w) in [-1/2, 1/2] in FP64, then the gfx950 hardware sine and cosine
-// (argument in revolutions) on float(u).
-__device__ __forceinline__ void phase_rev(double g2pi, double cz, float &c, float &s)
-{
-    const double w = g2pi * cz;
-    const float u = (float)(w - rint(w));
-    s = __builtin_amdgcn_sinf(u);
-    c = __builtin_amdgcn_cosf(u);
-}
-
-// Scheduling fence after every 4th register of a loop that reads the cost
-// diagonal: bounds how many FP64 loads and their consumers are in flight.
-#define QQ_CHUNK_FENCE(r)                                   \
-    if (((r) & 3) == 3) __builtin_amdgcn_sched_barrier(0)
-
-// Global-memory access through a wave-uniform 64-bit base and a 32-bit per-thread offset.
-template <typename T>
-__device__ __forceinline__ T gld(uint64_t sbase, uint32_t voff)
-{
-    if constexpr (std::is_same<T, float2>::value) {
-        // state amplitudes are streamed once per pass: non-temporal
-        const uint64_t u =
-            __builtin_nontemporal_load(reinterpret_cast<const uint64_t __attribute__((address_space(1))) *>(sbase + voff));
-        return make_float2(__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32)));
-    } else {
-        return *reinterpret_cast<const T __attribute__((address_space(1))) *>(sbase + voff);
-    }
-}
-__device__ __forceinline__ void gst(uint64_t sbase, uint32_t voff, float2 x)
-{
-    const uint64_t u = (uint64_t)__float_as_uint(x.x) | ((uint64_t)__float_as_uint(x.y) << 32);
-    __builtin_nontemporal_store(u, reinterpret_cast<uint64_t __attribute__((address_space(1))) *>(sbase + voff));
-}
-// A value the optimiser must treat as unknown at this point (keeps uses inside the loop).
-__device__ __forceinline__ uint64_t opaque_u64(uint64_t x)
-{
-    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    asm volatile("" : "+s"(lo), "+s"(hi));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-struct MixCoef {
-    float m;      // t (form A) or u (form B), direction folded in
-    int formB;
-    float scale;  // sigma^(active qubits), applied after the operation
-    double sig2;  // sigma^2
-};
-
-__device__ __forceinline__ MixCoef mix_coef(double beta, bool inverse, int nact)
-{
-    double s, c;
-    sincos(beta, &s, &c);
-    MixCoef r;
-    double sigma;
-    if (fabs(c) >= fabs(s)) {
-        const float t = (float)(s / c);
-        r.formB = 0;
-        r.m = inverse ? -t : t;
-        sigma = copysign(1.0, c) / sqrt(fma((double)t, (double)t, 1.0));
-    } else {
-        const float u = (float)(c / s);
-        r.formB = 1;
-        r.m = inverse ? -u : u;
-        sigma = copysign(1.0, s) / sqrt(fma((double)u, (double)u, 1.0));
-        if (inverse) sigma = -sigma;
-    }
-    r.sig2 = sigma * sigma;
-    double sc = 1.0;
-    for (int i = 0; i < nact; ++i) sc *= sigma;
-    r.scale = (float)sc;
-    return r;
-}
-
-// Scheduling fences between butterfly stages keep the stages in place (each
-// stage is in-register and needs no temporaries); without them the scheduler
-// interleaves stages and the register demand grows past the occupancy target.
-#define QQ_STAGE_FENCE() __builtin_amdgcn_sched_barrier(0)
-
-// Scheduling fence after every 4th register of a loop that reads the cost
-// diagonal: bounds how many FP64 loads and their consumers are in flight.
-#define QQ_CHUNK_FENCE(r)                                   \
-    if (((r) & 3) == 3) __builtin_amdgcn_sched_barrier(0)
-
-// Butterfly of bit K: form A  (a, b) -> (a - i t b, b - i t a);
-//                     form B  (a, b) -> (u a - i b, u b - i a).
-template <int K, bool FB>
-__device__ __forceinline__ void bf(float2 (&v)[kRegs], float m)
-{
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r) {
-        if (r & (1 << K)) continue;
-        const float2 a = v[r], b = v[r | (1 << K)];
-        if constexpr (FB) {
-            v[r] = make_float2(fmaf(m, a.x, b.y), fmaf(m, a.y, -b.x));
-            v[r | (1 << K)] = make_float2(fmaf(m, b.x, a.y), fmaf(m, b.y, -a.x));
-        } else {
-            v[r] = make_float2(fmaf(m, b.y, a.x), fmaf(-m, b.x, a.y));
-            v[r | (1 << K)] = make_float2(fmaf(m, a.y, b.x), fmaf(-m, a.x, b.y));
-        }
-    }
-}
-
-template <bool FB>
-__device__ __forceinline__ void group_mix(float2 (&v)[kRegs], int mask, float m)
-{
-    if (mask & 1) bf<0, FB>(v, m);
-    QQ_STAGE_FENCE();
-    if (mask & 2) bf<1, FB>(v, m);
-    QQ_STAGE_FENCE();
-    if (mask & 4) bf<2, FB>(v, m);
-    QQ_STAGE_FENCE();
-    if (mask & 8) bf<3, FB>(v, m);
-    QQ_STAGE_FENCE();
-}
-
-// sum over the active bits K of the group and the register pairs (r, r | 2^K) of
-// Im(conj(l_r) a_{r|2^K} + conj(l_{r|2^K}) a_r)  =  sum_K Im <l| X_K |a>  restricted to the thread's registers.
-template <int K>
-__device__ __forceinline__ float xexp_bit(const float2 (&a)[kRegs], const float2 (&l)[kRegs], float acc)
-{
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r) {
-        if (r & (1 << K)) continue;
-        const int q = r | (1 << K);
-        acc = fmaf(l[r].x, a[q].y, acc);
-        acc = fmaf(-l[r].y, a[q].x, acc);
-        acc = fmaf(l[q].x, a[r].y, acc);
-        acc = fmaf(-l[q].y, a[r].x, acc);
-    }
-    return acc;
-}
-
-__device__ __forceinline__ float xexp_group(const float2 (&a)[kRegs], const float2 (&l)[kRegs], int mask)
-{
-    float acc = 0.0f;
-    if (mask & 1) acc = xexp_bit<0>(a, l, acc);
-    QQ_STAGE_FENCE();
-    if (mask & 2) acc = xexp_bit<1>(a, l, acc);
-    QQ_STAGE_FENCE();
-    if (mask & 4) acc = xexp_bit<2>(a, l, acc);
-    QQ_STAGE_FENCE();
-    if (mask & 8) acc = xexp_bit<3>(a, l, acc);
-    QQ_STAGE_FENCE();
-    return acc;
-}
-
-template <int FROM, int TO>
-__device__ __forceinline__ void xpose(float2 *lds, float2 (&v)[kRegs], int t)
-{
-    __syncthreads();
-    lds_put<FROM>(lds, v, t, 0);
-    __syncthreads();
-    lds_get<TO>(lds, v, t, 0);
-}
-
-// Live states: ST bit 0 = psi (v[0]), bit 1 = lambda (v[1]).
-template <int FROM, int TO, int NS, int ST>
-__device__ __forceinline__ void xpose_all(float2 *lds, float2 (&v)[NS][kRegs], int t)
-{
-    if constexpr (ST & 1) xpose<FROM, TO>(lds, v[0], t);
-    if constexpr (NS > 1 && (ST & 2)) xpose<FROM, TO>(lds, v[NS - 1], t);
-}
-
-template <int NS, int ST>
-__device__ __forceinline__ void scale_all(float2 (&v)[NS][kRegs], float s)
-{
-#pragma unroll
-    for (int r = 0; r < kRegs; ++r) {
-        if constexpr (ST & 1) v[0][r] = make_float2(v[0][r].x * s, v[0][r].y * s);
-        if constexpr (NS > 1 && (ST & 2)) v[NS - 1][r] = make_float2(v[NS - 1][r].x * s, v[NS - 1][r].y * s);
-    }
-}
-
-__device__ __forceinline__ double pow_int(double x, int k)
-{
-    double r = 1.0;
-    for (int i = 0; i < k; ++i) r *= x;
-    return r;
-}
-
-// One mixer operation on the active tile bits, starting in layout FROM (2 or 1)
-// and ending in the other one.  GB: accumulate sum_q Im<lambda|X_q|psi> (both states
-// live); each group's partial is taken before its butterflies and rescaled by
-// sigma^(2 done), where done = bits already mixed by the unnormalised factor M.
-template <bool HIGH, bool FULL, int FROM, int NS, int ST, bool GB, bool FB>
-__device__ __forceinline__ void mix_op(float2 *lds, float2 (&v)[NS][kRegs], int t, int active, const MixCoef &c,
-                                       double &gacc)
-{
-    // FULL: every bit of the set's register groups is active (compile-time masks).
-    const int m0 = FULL ? (HIGH ? 0 : 15) : (active & 15);
-    const int m1 = FULL ? 15 : ((active >> 4) & 15);
-    const int m2 = FULL ? 15 : ((active >> 8) & 15);
-    int done = 0;
-    auto group = [&](int mask) {
-        if constexpr (GB) {
-            const float x = xexp_group(v[0], v[1], mask);
-            gacc = fma((double)x, pow_int(c.sig2, done), gacc);
-        }
-        if constexpr (ST & 1) group_mix<FB>(v[0], mask, c.m);
-        if constexpr (NS > 1 && (ST & 2)) group_mix<FB>(v[NS - 1], mask, c.m);
-        done += __popc(mask);
-    };
-    if constexpr (!HIGH) {
-        if constexpr (FROM == 2) {
-            group(m2);
-            xpose_all<2, 0, NS, ST>(lds, v, t);
-            group(m0);
-            xpose_all<0, 1, NS, ST>(lds, v, t);
-            group(m1);
-        } else {
-            group(m1);
-            xpose_all<1, 0, NS, ST>(lds, v, t);
-            group(m0);
-            xpose_all<0, 2, NS, ST>(lds, v, t);
-            group(m2);
-        }
-    } else {
-        if constexpr (FROM == 2) {
-            group(m2);
-            xpose_all<2, 1, NS, ST>(lds, v, t);
-            group(m1);
-        } else {
-            group(m1);
-            xpose_all<1, 2, NS, ST>(lds, v, t);
-            group(m2);
-        }
-    }
-    scale_all<NS, ST>(v, c.scale);
-}
-
-// Pass kinds (FastPassKind):
-//   FK_FIRST  init, phase(0), mix(0)                                         -> psi
-//   FK_MID    psi: mix(k)                                                    -> psi
-//   FK_TURN   psi: mix(k), phase(k+1), mix(k+1)                              -> psi
-//   FK_LAST   psi: mix(k), energy                                            (-> psi)
-//   FK_LASTG  psi: mix(k), energy, lambda = C psi, unmix(k) + g_beta(k)      -> lambda
-//   FK_BMID   psi, lambda: unmix(k) + g_beta(k)                              -> psi, lambda
-//   FK_BTURN  psi, lambda: unmix(k) + g_beta(k), g_gamma(k), unphase(k), unmix(k-1) + g_beta(k-1)
-//   FK_BLAST  psi, lambda: unmix(0) + g_beta(0), g_gamma(0)
-
-struct FastArgs {
-    int B, G, p, k;
-    uint64_t tiles;
-    uint64_t dim_mask;
-    int pos4, pos8, w1, w2, active, nact;
-    int store_psi;
-    int slot_base, slot_stride;
-    double amp0;
-    const double *params;
-    const void *diag;
-    float2 *psi;
-    float2 *lam;
-    uint64_t state_stride;
-    double *partial;
-};
-
-template <int KIND>
-constexpr int kind_states()
-{
-    return KIND >= FK_LASTG ? 2 : 1;
-}
-template <int KIND>
-constexpr int kind_slots()
-{
-    return KIND == FK_LAST ? 1 : KIND == FK_LASTG ? 2 : KIND == FK_BMID ? 1 : KIND == FK_BTURN ? 3
-           : KIND == FK_BLAST ? 2 : 0;
-}
-
-// The tile loop of one pass kind.  FB1 / FB2: form of the first / second mixer coefficient.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool FB1, bool FB2>
-__device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g,
-                                          const MixCoef &c1, const MixCoef &c2, double g2pi)
-{
-    constexpr int NS = kind_states<KIND>();
-    // Global addressing.  Tile-local bits 0..3 and the two lane bits above them
-    // vary per thread (a 32-bit byte offset); the two wave bits and the four
-    // register bits are wave-uniform and go into a 64-bit scalar base per register.
-    //   layout 2: lanes -> qubits 0..3, pos4, pos4+1; waves -> pos4+2, pos4+3; registers -> pos8..pos8+3
-    //   layout 1: lanes -> qubits 0..3, pos8, pos8+1; waves -> pos8+2, pos8+3; registers -> pos4..pos4+3
-    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(t >> 6);
-    const uint32_t lane_lo = t & 15, lane_hi = (t >> 4) & 3;
-    const uint32_t e2 = lane_lo + (lane_hi << a.pos4), e1 = lane_lo + (lane_hi << a.pos8);
-    const uint32_t vs2 = e2 * (uint32_t)sizeof(float2), vs1 = e1 * (uint32_t)sizeof(float2);
-    const uint32_t vd2 = e2 * (uint32_t)sizeof(DT), vd1 = e1 * (uint32_t)sizeof(DT);
-    const uint64_t w2 = (uint64_t)wave << (a.pos4 + 2), w1 = (uint64_t)wave << (a.pos8 + 2);
-    const uint64_t psi_a = (uint64_t)(a.psi + (size_t)b * a.state_stride);
-    const uint64_t lam_a = (uint64_t)(a.lam + (size_t)b * a.state_stride);
-    const uint64_t diag_a = (uint64_t)a.diag;
-    float2 v[NS][kRegs];
-
-    for (uint64_t tile = g; tile < a.tiles; tile += a.G) {
-        uint64_t base;
-        if constexpr (HIGH) base = tile_base(tile, a.pos4, a.pos8, a.w1, a.w2);
-        else base = tile << kTileBits;
-        // register strides, opaque per tile so their multiples are formed in scalar
-        // registers at each use rather than hoisted out of the loop
-        const uint64_t rs2 = opaque_u64(1ull << a.pos8), rs1 = opaque_u64(1ull << a.pos4);
-        const uint64_t b2 = base + w2, b1 = base + w1;
-        auto cz2 = [&](int r) { return (double)gld<DT>(diag_a + (b2 + r * rs2) * sizeof(DT), vd2); };
-        auto cz1 = [&](int r) { return (double)gld<DT>(diag_a + (b1 + r * rs1) * sizeof(DT), vd1); };
-        auto ld2 = [&](uint64_t arr, int r) { return gld<float2>(arr + (b2 + r * rs2) * 8, vs2); };
-        // stores take their own opaque copy of the stride: sharing the load addresses
-        // would keep 16-32 scalar address pairs live across the whole tile
-        auto st2f = [&](uint64_t arr, int r, float2 x, uint64_t rs) { gst(arr + (b2 + r * rs) * 8, vs2, x); };
-        auto st1f = [&](uint64_t arr, int r, float2 x, uint64_t rs) { gst(arr + (b1 + r * rs) * 8, vs1, x); };
-
-        if constexpr (KIND == FK_FIRST) {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) {
-                float c, s;
-                phase_rev(g2pi, cz2(r), c, s);
-                v[0][r] = make_float2((float)a.amp0 * c, -(float)a.amp0 * s);
-                QQ_CHUNK_FENCE(r);
-            }
-            double unused = 0.0;
-            mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
-            const uint64_t rss = opaque_u64(rs1);
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
-        } else if constexpr (KIND == FK_MID || KIND == FK_TURN || KIND == FK_LAST) {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) v[0][r] = ld2(psi_a, r);
-            double unused = 0.0;
-            mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
-            if constexpr (KIND == FK_MID) {
-                const uint64_t rss = opaque_u64(rs1);
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
-            } else if constexpr (KIND == FK_TURN) {
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) {
-                    float c, s;
-                    phase_rev(g2pi, cz1(r), c, s);
-                    rot_phase<float>(v[0][r], c, s);
-                    QQ_CHUNK_FENCE(r);
-                }
-                mix_op<HIGH, FULL, 1, 1, 1, false, FB2>(lds, v, t, a.active, c2, unused);
-                const uint64_t rss = opaque_u64(rs2);
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) st2f(psi_a, r, v[0][r], rss);
-            } else {
-                double e = 0.0;
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) {
-                    const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
-                    e = fma((double)pz, cz1(r), e);
-                    QQ_CHUNK_FENCE(r);
-                }
-                acc[0] += e;
-                if (a.store_psi) {
-                    const uint64_t rss = opaque_u64(rs1);
-#pragma unroll
-                    for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
-                }
-            }
-        } else if constexpr (KIND == FK_LASTG) {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) v[0][r] = ld2(psi_a, r);
-            double gb = 0.0;
-            mix_op<HIGH, FULL, 2, 2, 1, false, FB1>(lds, v, t, a.active, c1, gb);
-            double e = 0.0;
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) {
-                const double cz = cz1(r);
-                const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
-                e = fma((double)pz, cz, e);
-                const float cf = (float)cz;
-                v[1][r] = make_float2(cf * v[0][r].x, cf * v[0][r].y);
-                QQ_CHUNK_FENCE(r);
-            }
-            acc[0] += e;
-            mix_op<HIGH, FULL, 1, 2, 3, true, FB2>(lds, v, t, a.active, c2, gb);
-            acc[1] += gb;
-            const uint64_t rss = opaque_u64(rs2);
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) st2f(lam_a, r, v[1][r], rss);
-        } else {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) {
-                v[0][r] = ld2(psi_a, r);
-                v[1][r] = ld2(lam_a, r);
-            }
-            double gb = 0.0;
-            mix_op<HIGH, FULL, 2, 2, 3, true, FB1>(lds, v, t, a.active, c1, gb);
-            acc[0] += gb;
-            if constexpr (KIND == FK_BMID) {
-                const uint64_t rss = opaque_u64(rs1);
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) {
-                    st1f(psi_a, r, v[0][r], rss);
-                    st1f(lam_a, r, v[1][r], rss);
-                }
-            } else {
-                double gg = 0.0;
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) {
-                    const double cz = cz1(r);
-                    const float2 ps = v[0][r], la = v[1][r];
-                    const float im = fmaf(la.x, ps.y, -la.y * ps.x);
-                    gg = fma(cz, (double)im, gg);
-                    if constexpr (KIND == FK_BTURN) {
-                        float c, s;
-                        phase_rev(g2pi, cz, c, s);
-                        rot_phase<float>(v[0][r], c, -s);
-                        rot_phase<float>(v[1][r], c, -s);
-                    }
-                    QQ_CHUNK_FENCE(r);
-                }
-                acc[1] += gg;
-                if constexpr (KIND == FK_BTURN) {
-                    double gb2 = 0.0;
-                    mix_op<HIGH, FULL, 1, 2, 3, true, FB2>(lds, v, t, a.active, c2, gb2);
-                    acc[2] += gb2;
-                    const uint64_t rss = opaque_u64(rs2);
-#pragma unroll
-                    for (int r = 0; r < kRegs; ++r) {
-                        st2f(psi_a, r, v[0][r], rss);
-                        st2f(lam_a, r, v[1][r], rss);
-                    }
-                }
-            }
-        }
-    }
-}
+using namespace passes;
 
 template <int KIND, bool HIGH, bool FULL, typename DT>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KIND >= FK_LASTG ? 3 : 4)))
@@ -462,43 +19,8 @@ fast_pass(const FastArgs a)
     const int t = threadIdx.x;
     int b, g;
     block_coords(a.B, a.G, b, g);
-    const double *x = a.params + (size_t)b * 2 * a.p;
-
-    // layer constants (uniform)
-    MixCoef c1{}, c2{};
-    double gam = 0.0;
-    if constexpr (KIND == FK_FIRST) {
-        gam = x[0];
-        c1 = mix_coef(x[1], false, a.nact);
-    } else if constexpr (KIND == FK_MID || KIND == FK_LAST) {
-        c1 = mix_coef(x[2 * a.k + 1], false, a.nact);
-    } else if constexpr (KIND == FK_TURN) {
-        c1 = mix_coef(x[2 * a.k + 1], false, a.nact);
-        gam = x[2 * (a.k + 1)];
-        c2 = mix_coef(x[2 * (a.k + 1) + 1], false, a.nact);
-    } else if constexpr (KIND == FK_LASTG) {
-        c1 = mix_coef(x[2 * a.k + 1], false, a.nact);
-        c2 = mix_coef(x[2 * a.k + 1], true, a.nact);
-    } else if constexpr (KIND == FK_BMID || KIND == FK_BLAST) {
-        c1 = mix_coef(x[2 * a.k + 1], true, a.nact);
-    } else if constexpr (KIND == FK_BTURN) {
-        c1 = mix_coef(x[2 * a.k + 1], true, a.nact);
-        gam = x[2 * a.k];
-        c2 = mix_coef(x[2 * (a.k - 1) + 1], true, a.nact);
-    }
-    const double g2pi = gam * QQ_INV_TWO_PI;
-
-    // One uniform dispatch per workgroup on the forms of the two coefficients,
-    // so the butterfly code of each path has no form branch.
     double acc[3] = {0.0, 0.0, 0.0};
-    constexpr bool TWO = KIND == FK_TURN || KIND == FK_LASTG || KIND == FK_BTURN;
-    const int sel = (c1.formB ? 1 : 0) | (TWO && c2.formB ? 2 : 0);
-    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
-    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, true, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
-    else if constexpr (TWO) {
-        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, false, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
-        else pass_body<KIND, HIGH, FULL, DT, true, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
-    }
+    run_pass<KIND, HIGH, FULL, DT>(a, lds, acc, t, b, g);
 
     if constexpr (NSLOT > 0) {
         const int lane = t & 63, wave = t >> 6;

@@ -130,7 +130,7 @@ hipError_t launch_local_tables(int n, int diag_type, const PartDesc *d_pd, const
                                uint64_t total, hipStream_t s);
 
 // Specialised complex64 pass kernels (qq_fast.hip): one kernel per pass kind.
-enum FastPassKind : int { FK_FIRST = 0, FK_MID, FK_TURN, FK_LAST, FK_LASTG, FK_BMID, FK_BTURN, FK_BLAST };
+enum FastPassKind : int { FK_FIRST = 0, FK_MID, FK_TURN, FK_LAST, FK_LASTG, FK_BMID, FK_BTURN, FK_BLAST, FK_SINGLE };
 struct FastPassParams {
     int B, G, p, k;
     uint64_t tiles, dim_mask;
@@ -145,6 +145,51 @@ struct FastPassParams {
     double *partial;
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
+
+// Persistent launch over many problems (qq_many.hip).
+// Work item = (problem, state b, pass j, chunk c): tiles [c * tpc, min((c + 1) * tpc, tiles))
+// of pass j.  Items are numbered level-major (every problem's pass 0, then every
+// problem's pass 1, ...) and taken in that order from one atomic ticket counter,
+// so an item only ever waits for items with smaller tickets.
+struct ManyInst {
+    int n, p, B;
+    int npasses, pass_off;  // passes in ManyPass[pass_off ..]
+    int nchunks, tpc;
+    int nslots, slot_off;   // accumulator slots; their output indices in slot_out[slot_off ..]
+    int state0;             // counter index of state 0
+    uint64_t tiles, dim_mask;
+    uint64_t partial_off;   // doubles, laid out [slot][b][chunk]
+    double amp0, escale;
+    const double *params;   // device [B][2p]
+    const void *diag;
+    void *psi, *lam;        // device [B][2^n] complex64 (multi-pass problems)
+    double *energy_out;     // device [B], or NULL: results go to out_ws
+    double *grad_out;       // device [B][2p] (with energy_out)
+    double *out_ws;         // device [B][1 + 2p]
+};
+struct ManyPass {
+    int kind, k, geom;      // geom 0: qubits 0..11; 1: high set, all 8 bits active; 2: high set, partial
+    int pos4, pos8, w1, w2, active, nact, store_psi;
+    int slot_base, nslots;  // first accumulator slot of the pass inside its problem
+};
+struct ManySeg {
+    uint32_t first;  // ticket of chunk 0
+    uint32_t inst, b, pass;
+};
+struct ManyArgs {
+    const ManyInst *inst;
+    const ManyPass *pass;
+    const ManySeg *seg;
+    const uint16_t *slot_out;
+    int nseg;
+    int grad;
+    uint32_t total;       // tickets
+    uint32_t *ctl;        // [0] ticket head, [1] error flag, [2 + s] items completed for state s
+    double *partial;
+    uint64_t spin_ticks;  // bound on one dependency wait, in wall-clock ticks
+};
+hipError_t launch_many(const ManyArgs &a, int diag_type, int max_grid, hipStream_t s, int *grid_out);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 
 // Plain complex128 per-gate path (qq_plain.hip).
 struct PlainArgs {

@@ -61,6 +61,11 @@ class QQInfo(ctypes.Structure):
                 ("cross_terms", ctypes.c_int64)]
 
 
+class QQManyOptions(ctypes.Structure):
+    _fields_ = [("tiles_per_chunk", ctypes.c_int), ("max_workgroups", ctypes.c_int),
+                ("wait_limit_ms", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -85,6 +90,9 @@ SIGNATURES = {
     "qq_probabilities": ([_vp, _int, _vp, _int, _vp, _vp], _int),
     "qq_topk": ([_vp, _int, _vp, _int, _int, _u64p, _dp, _dp, _vp], _int),
     "qq_evaluate_plain": ([_vp, _int, _dp, _int, _vp, _dp, _dp], _int),
+    "qq_workspace_size_many": ([_int, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), _szp], _int),
+    "qq_evaluate_many": ([_int, _vp, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), _vp, ctypes.c_size_t, _vp,
+                          _vp, _vp], _int),
     "qq_profile_enable": ([_int], _int),
     "qq_profile_read": ([ctypes.c_void_p, _int, ctypes.POINTER(_int)], _int),
 }
@@ -262,6 +270,55 @@ def qq_evaluate_plain(handle, p, params, flags, stream=None):
     return float(e[0]), g
 
 
+def _many_options(opt):
+    if opt is None:
+        return None
+    o = QQManyOptions(int(opt.get("tiles_per_chunk", 0)), int(opt.get("max_workgroups", 0)),
+                      float(opt.get("wait_limit_ms", 0.0)))
+    return ctypes.pointer(o)
+
+
+def _many_arrays(handles, p, batch):
+    count = len(handles)
+    hs = (_vp * count)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    pa = np.ascontiguousarray(p, dtype=np.int32)
+    ba = np.ascontiguousarray(batch, dtype=np.int32)
+    if pa.shape != (count,) or ba.shape != (count,):
+        raise ValueError("p and batch need one entry per problem")
+    return count, hs, pa, ba
+
+
+def qq_workspace_size_many(handles, p, batch, flags, opt=None) -> int:
+    count, hs, pa, ba = _many_arrays(handles, p, batch)
+    s = ctypes.c_size_t(0)
+    _check(lib().qq_workspace_size_many(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
+                                        int(flags), _many_options(opt), ctypes.byref(s)))
+    return s.value
+
+
+def qq_evaluate_many(handles, p, batch, params, flags, opt, workspace, ws_bytes, stream, energy_out, grad_out):
+    """params[i], energy_out[i], grad_out[i]: numpy arrays, or device tensors with the *_ON_DEVICE flags;
+    grad_out may be None without QQ_GRAD."""
+    count, hs, pa, ba = _many_arrays(handles, p, batch)
+
+    def ptr(a, dev):
+        return (int(a.data_ptr()) if dev else a.ctypes.data) if a is not None else None
+
+    pin = flags & QQ_PARAMS_ON_DEVICE
+    pout = flags & QQ_OUT_ON_DEVICE
+    for i in range(count):
+        if not pin and (params[i].dtype != np.float64 or not params[i].flags["C_CONTIGUOUS"]):
+            raise ValueError("params[%d] must be a C-contiguous float64 array" % i)
+    pp = (_vp * count)(*[ptr(params[i], pin) for i in range(count)])
+    ep = (_vp * count)(*[ptr(energy_out[i], pout) for i in range(count)])
+    gp = (_vp * count)(*[ptr(grad_out[i], pout) if grad_out is not None else None for i in range(count)])
+    wp = None if workspace is None else _dev_ptr(workspace)
+    _check(lib().qq_evaluate_many(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
+                                  ctypes.cast(pp, _vp), int(flags), _many_options(opt), wp, int(ws_bytes),
+                                  _stream_ptr(stream), ctypes.cast(ep, _vp),
+                                  ctypes.cast(gp, _vp) if grad_out is not None else None))
+
+
 def qq_profile_enable(enable: bool):
     _check(lib().qq_profile_enable(1 if enable else 0))
 
@@ -283,6 +340,8 @@ def kernel_name(rec) -> str:
     """The kernel instantiation a launch record belongs to, in rocprofv3's naming."""
     if rec["kind"] == 3:
         return "finalize_kernel"
+    if rec["kind"] == 4:
+        return f"many_kernel<{DIAG_TYPE_NAMES[rec['diag_bytes']]}>"
     dt = DIAG_TYPE_NAMES[rec["diag_bytes"]]
     if rec["pass_kind"] >= 0:
         tf = lambda x: "true" if x else "false"  # noqa: E731

@@ -96,6 +96,40 @@ class Problem:
         return N.qq_evaluate_plain(self.handle, x.shape[0] // 2, x, N.QQ_GRAD if grad else N.QQ_ENERGY)
 
 
+def evaluate_many(problems, params, grad=False, options=None, workspace=None):
+    """Energies (and gradients) of many problems in one persistent launch per diagonal type.
+
+    problems: list of Problem; params: list of [B_i, 2p_i] arrays (numpy: host path) or
+    CUDA tensors (device path).  options: dict with tiles_per_chunk, max_workgroups,
+    wait_limit_ms (0 = automatic).  Returns (energies, grads) as lists (grads None without grad).
+    """
+    import torch
+
+    flags = N.QQ_ENERGY | (N.QQ_GRAD if grad else 0)
+    handles = [pb.handle for pb in problems]
+    dev = len(params) > 0 and isinstance(params[0], torch.Tensor) and params[0].is_cuda
+    if dev:
+        xs = [x.detach().to(torch.float64).contiguous() for x in params]
+        device = xs[0].device
+        flags |= N.QQ_PARAMS_ON_DEVICE | N.QQ_OUT_ON_DEVICE
+        e = [torch.empty(x.shape[0], dtype=torch.float64, device=device) for x in xs]
+        g = [torch.empty(x.shape, dtype=torch.float64, device=device) for x in xs] if grad else None
+    else:
+        xs = [np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64) for x in params]
+        e = [np.empty(x.shape[0]) for x in xs]
+        g = [np.empty(x.shape) for x in xs] if grad else None
+    ps = [x.shape[1] // 2 for x in xs]
+    bs = [x.shape[0] for x in xs]
+    stream = None
+    ws, ws_bytes = None, 0
+    if dev:
+        ws_bytes = N.qq_workspace_size_many(handles, ps, bs, flags, options)
+        ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+        stream = torch.cuda.current_stream(device)
+    N.qq_evaluate_many(handles, ps, bs, xs, flags, options, ws, ws_bytes, stream, e, g)
+    return e, g
+
+
 def _make_autograd():
     import torch
 

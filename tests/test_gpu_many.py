@@ -1,0 +1,212 @@
+"""GPU parity of the persistent many-problem launch (qq_evaluate_many) through the C ABI.
+
+References: the FP64 oracle (energy and adjoint gradient) on every problem small
+enough for it, and per-problem qq_evaluate calls (the per-launch path).
+Tolerances: 1e-5 relative against the oracle (energy |dE| / max(|E|, sigma_C),
+gradient ||dg||_inf / ||g||_inf); 1e-9 relative against qq_evaluate for n >= 13
+(same complex64 arithmetic per amplitude, only the order of the FP64 partial sums
+differs) and 1e-5 for n <= 12 (a different single-tile kernel); bit-identical
+results across grid sizes (fixed-order reductions).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_26297_amd import native as N
+from paper_2606_26297_amd import workloads as W
+from paper_2606_26297_amd.qaoa import Problem, evaluate_many
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    N.lib()
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def e_err(e, eref, sigma):
+    return float(np.max(np.abs(np.asarray(e) - np.asarray(eref)) / np.maximum(np.abs(eref), sigma)))
+
+
+def g_err(g, gref):
+    g, gref = np.atleast_2d(g), np.atleast_2d(gref)
+    return max(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300) for a, b in zip(g, gref))
+
+
+# uneven mix: single-tile sizes (n <= 12, incl. n < 4), two-set and three-set plans,
+# full and partial high sets, integer (int16 / int32) and real diagonals
+MIX = [(1, 2, 1), (3, 1, 2), (7, 3, 1), (11, 2, 2), (12, 4, 1), (13, 1, 1), (14, 3, 2), (16, 2, 1),
+       (17, 5, 1), (19, 2, 1), (20, 3, 2), (21, 2, 1), (22, 1, 1)]
+
+
+def mix_instances():
+    out = []
+    for k, (n, p, B) in enumerate(MIX):
+        if k % 3 == 0:
+            inst = W.dense_gaussian_upper(n, 300 + k)        # real FP64 diagonal
+        elif k % 3 == 1:
+            inst = W.dense_integer_symmetric(n, 300 + k)     # int16 diagonal
+        else:
+            inst = W.Instance(H=np.triu(np.random.default_rng(300 + k).integers(-3000, 3001, (n, n))).astype(float),
+                              f=np.zeros(n), c0=5.0)          # int32 diagonal
+        out.append((inst, W.random_params(p, B, 400 + k)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def mix():
+    insts = mix_instances()
+    pbs = [Problem(i.H, i.f, i.c0) for i, _ in insts]
+    return insts, pbs
+
+
+def test_mix_covers_every_diagonal_type(mix):
+    _, pbs = mix
+    assert sorted({pb.info.diag_bytes for pb in pbs}) == [2, 4, 8]
+
+
+def test_many_vs_oracle_and_per_problem(mix):
+    insts, pbs = mix
+    xs = [x for _, x in insts]
+    e, g = evaluate_many(pbs, xs, grad=True)
+    for k, ((inst, x), pb) in enumerate(zip(insts, pbs)):
+        n = pb.n
+        sig = pb.info.sigma_c
+        print(f"problem {k}: n={n} p={x.shape[1] // 2} B={x.shape[0]}", flush=True)
+        # per-problem launches
+        e1, g1 = pb.evaluate(x, grad=True)
+        tol = 1e-9 if n > 12 else 1e-5
+        assert e_err(e[k], e1, sig) <= tol, (k, e[k], e1)
+        assert g_err(g[k], g1) <= tol, k
+        # oracle (all of these sizes finish in seconds)
+        d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+        for b in range(x.shape[0]):
+            er, gr = O.gradient(d, x[b])
+            assert e_err(e[k][b], er, sig) <= 1e-5, (k, b)
+            assert g_err(g[k][b], gr) <= 1e-5, (k, b)
+
+
+def test_many_energy_only_matches_grad_run(mix):
+    insts, pbs = mix
+    xs = [x for _, x in insts]
+    e_only, g_none = evaluate_many(pbs, xs, grad=False)
+    assert g_none is None
+    e, _ = evaluate_many(pbs, xs, grad=True)
+    for k, pb in enumerate(pbs):
+        assert e_err(e_only[k], e[k], pb.info.sigma_c) <= 1e-9, k
+
+
+def test_many_bitwise_across_grid_sizes_and_repeat(mix):
+    insts, pbs = mix
+    xs = [x for _, x in insts]
+    ea, ga = evaluate_many(pbs, xs, grad=True)
+    eb, gb = evaluate_many(pbs, xs, grad=True, options={"max_workgroups": 7})
+    ec, gc = evaluate_many(pbs, xs, grad=True)
+    for k in range(len(pbs)):
+        assert np.array_equal(ea[k], eb[k]) and np.array_equal(ga[k], gb[k]), k
+        assert np.array_equal(ea[k], ec[k]) and np.array_equal(ga[k], gc[k]), k
+
+
+def test_many_chunk_sizes_agree(mix):
+    insts, pbs = mix
+    xs = [x for _, x in insts]
+    ea, ga = evaluate_many(pbs, xs, grad=True, options={"tiles_per_chunk": 1})
+    eb, gb = evaluate_many(pbs, xs, grad=True, options={"tiles_per_chunk": 64})
+    for k, pb in enumerate(pbs):
+        assert e_err(ea[k], eb[k], pb.info.sigma_c) <= 1e-9, k
+        assert g_err(ga[k], gb[k]) <= 1e-9, k
+
+
+def test_many_device_path_matches_host(mix):
+    import torch
+
+    insts, pbs = mix
+    xs = [x for _, x in insts]
+    eh, gh = evaluate_many(pbs, xs, grad=True)
+    xt = [torch.tensor(x, device="cuda:0") for x in xs]
+    ed, gd = evaluate_many(pbs, xt, grad=True)
+    torch.cuda.synchronize()
+    for k in range(len(pbs)):
+        assert np.array_equal(ed[k].cpu().numpy(), eh[k]) and np.array_equal(gd[k].cpu().numpy(), gh[k]), k
+
+
+def test_many_rejects_unsupported_and_bad_arguments(mix):
+    _, pbs = mix
+    x = [W.random_params(1, 1, 1)]
+    e = [np.empty(1)]
+    g = [np.empty((1, 2))]
+    with pytest.raises(N.QQError) as ei:
+        N.qq_evaluate_many([pbs[0].handle], [1], [1], x, N.QQ_ENERGY | N.QQ_C128, None, None, 0, None, e, g)
+    assert ei.value.status == N.QQ_E_UNSUPPORTED
+    with pytest.raises(N.QQError) as ei:
+        N.qq_evaluate_many([pbs[0].handle], [1], [0], x, N.QQ_ENERGY, None, None, 0, None, e, g)
+    assert ei.value.status == N.QQ_E_INVALID
+    with pytest.raises(N.QQError) as ei:
+        N.qq_evaluate_many([pbs[0].handle], [1], [1], [np.array([[0.1, np.nan]])], N.QQ_ENERGY, None, None, 0, None,
+                           e, g)
+    assert ei.value.status == N.QQ_E_INVALID
+    with pytest.raises(N.QQError) as ei:
+        N.qq_evaluate_many([pbs[0].handle], [1], [1], x, N.QQ_ENERGY | N.QQ_GRAD, None, None, 0, None, e, None)
+    assert ei.value.status == N.QQ_E_INVALID
+    with pytest.raises(N.QQError) as ei:
+        N.qq_evaluate_many([pbs[0].handle], [1], [1], x, N.QQ_ENERGY, {"tiles_per_chunk": -1}, None, 0, None, e, g)
+    assert ei.value.status == N.QQ_E_INVALID
+
+
+def test_many_wait_limit_reports_error_then_recovers(mix):
+    """A wait limit far below any pass time makes dependency waits run out: the flag
+    drains the launch and the call reports QQ_E_DEVICE; a normal call afterwards works."""
+    insts, pbs = mix
+    big = [k for k, (n, _, _) in enumerate(MIX) if n >= 20]
+    sub = [pbs[k] for k in big]
+    xs = [insts[k][1] for k in big]
+    with pytest.raises(N.QQError) as ei:
+        evaluate_many(sub, xs, grad=True, options={"wait_limit_ms": 1e-6})
+    assert ei.value.status == N.QQ_E_DEVICE
+    e, g = evaluate_many(sub, xs, grad=True)
+    for k, pb in zip(big, sub):
+        e1, g1 = pb.evaluate(insts[k][1], grad=True)
+        assert e_err(e[big.index(k)], e1, pb.info.sigma_c) <= 1e-9
+
+
+def test_workload4_many_vs_per_problem_launches():
+    """The uneven-batch workload (512 dense integer problems, n in 10..22, p in 1..6):
+    one persistent launch against 512 per-problem qq_evaluate calls, and the oracle
+    on a sample of the small problems."""
+    items = W.workload4()
+    pbs = [Problem(i.H, i.f, i.c0) for i, _ in items]
+    xs = [x for _, x in items]
+    e, g = evaluate_many(pbs, xs, grad=True)
+    # both paths are complex64 (each within 1e-5 of FP64): they agree to 2e-5, and the
+    # problem where they differ most is checked against the oracle on both sides
+    de, dg = [], []
+    per = []
+    for k, ((inst, x), pb) in enumerate(zip(items, pbs)):
+        e1, g1 = pb.evaluate(x, grad=True)
+        per.append((e1, g1))
+        de.append(e_err(e[k], e1, pb.info.sigma_c))
+        dg.append(g_err(g[k], g1))
+    print(f"workload4: many vs per-problem: worst energy rel {max(de):.3e}, worst grad rel {max(dg):.3e}", flush=True)
+    assert max(de) <= 2e-5 and max(dg) <= 2e-5
+    for k in sorted({int(np.argmax(de)), int(np.argmax(dg))}):
+        inst, x = items[k]
+        d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+        er, gr = O.gradient(d, x[0])
+        sig = pbs[k].info.sigma_c
+        errs = (e_err(e[k][0], er, sig), g_err(g[k][0], gr), e_err(per[k][0][0], er, sig), g_err(per[k][1][0], gr))
+        print(f"  problem {k} (n={pbs[k].n}, p={x.shape[1] // 2}) vs oracle: many E {errs[0]:.2e} g {errs[1]:.2e}; "
+              f"per-problem E {errs[2]:.2e} g {errs[3]:.2e}", flush=True)
+        assert max(errs) <= 1e-5, (k, errs)
+    checked = 0
+    for k, ((inst, x), pb) in enumerate(zip(items, pbs)):
+        if pb.n > 16 or checked >= 24:
+            continue
+        d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+        er, gr = O.gradient(d, x[0])
+        assert e_err(e[k][0], er, pb.info.sigma_c) <= 1e-5, k
+        assert g_err(g[k][0], gr) <= 1e-5, k
+        checked += 1
+    assert checked == 24
