@@ -216,7 +216,7 @@ qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int 
  * QQ_E_NOMEM, QQ_E_DEVICE.
  */
 typedef struct {
-    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: automatic */
+    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: 16 */
     int max_workgroups;    /* cap on the persistent grid; 0: every workgroup that fits on the device at once */
     double wait_limit_ms;  /* bound on one dependency wait; 0: 2000 ms */
 } qq_many_options;
@@ -227,6 +227,50 @@ qq_status qq_workspace_size_many(int count, qq_problem *const *problems, const i
 qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p, const int *batch,
                            const double *const *params, int flags, const qq_many_options *opt, void *workspace,
                            size_t ws_bytes, void *stream, double *const *energy_out, double *const *grad_out);
+
+/*
+ * Optimisation steps [energy + gradient -> Adam] captured once in a HIP graph
+ * and replayed (optimisation-overhead section: Adam with a cheaper gradient,
+ * here the exact adjoint one; throughput subsection: parallel multi-start runs,
+ * here `batch` starts stepping together).
+ *
+ * qq_graph_create captures one step for `batch` starts of depth p:
+ *   params   device [batch][2p] doubles, interleaved like qq_evaluate's; the
+ *            caller owns them, every step updates them in place
+ *   adam     4 host doubles {lr, beta1, beta2, eps}, or NULL for
+ *            {0.01, 0.9, 0.999, 1e-8}; per parameter, with t the step number:
+ *            m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ *            x -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
+ *   history  number of past steps whose energies are kept (ring buffer), or 0
+ *   flags    QQ_C128 / QQ_PARTITIONED as for qq_evaluate (QQ_GRAD is implied;
+ *            no *_ON_DEVICE flags)
+ * The handle owns the evaluation workspace, the Adam moments, the step counter
+ * and the last step's energies and gradients (all device memory, allocated here
+ * once).  The step counter and moments start at zero.  The problem handle and
+ * params must outlive the graph.
+ * qq_graph_run       replays the captured step `steps` times on `stream`
+ *                    (asynchronous; no allocation, no host work per step).
+ * qq_graph_step_eager launches the same kernels directly (one step).
+ * qq_graph_reset     zeroes the moments and the step counter (kernels on `stream`).
+ * qq_graph_read      copies the last step's energies (batch; taken at the
+ *                    parameters before that step's update) and gradients
+ *                    (batch x 2p), the energy history (history x batch, entry
+ *                    (t-1) mod history holds step t) and the number of steps
+ *                    taken; any output may be NULL; host memory unless
+ *                    QQ_OUT_ON_DEVICE (steps is always host); synchronises `stream`.
+ * Errors: QQ_E_INVALID, QQ_E_ALLOCATION, QQ_E_UNSUPPORTED, QQ_E_TOO_LARGE,
+ * QQ_E_NOMEM, QQ_E_DEVICE.
+ */
+typedef struct qq_graph qq_graph;
+
+qq_status qq_graph_create(qq_problem *prob, int p, int batch, int flags, const double *adam, double *params,
+                          int history, void *stream, qq_graph **out);
+qq_status qq_graph_run(qq_graph *graph, int steps, void *stream);
+qq_status qq_graph_step_eager(qq_graph *graph, void *stream);
+qq_status qq_graph_reset(qq_graph *graph, void *stream);
+qq_status qq_graph_read(qq_graph *graph, double *energy, double *grad, double *history, int *steps, int flags,
+                        void *stream);
+qq_status qq_graph_destroy(qq_graph *graph);
 
 /*
  * Measurement baseline: the plain complex128 form with one kernel per gate

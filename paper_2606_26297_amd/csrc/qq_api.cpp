@@ -433,8 +433,9 @@ double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128)
 
 // Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
 qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int B, int flags, char *ws,
-                   const double *d_params, hipStream_t stream)
+                   const double *d_params, hipStream_t stream, bool capturing = false)
 {
+    const bool prof = g_prof && !capturing;  // no event records inside a captured graph
     const bool c128 = flags & QQ_C128;
     const uint64_t T = tiles_per_state(pb->n);
     const size_t es = c128 ? 16 : 8;
@@ -477,7 +478,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
         a.part = pb->d_part;
         for (size_t i = 0; i < pp.ops.size(); ++i) a.ops[i] = pp.ops[i];
         ProfRec rec{};
-        if (g_prof) {
+        if (prof) {
             QQ_HIP(hipEventCreate(&rec.start));
             QQ_HIP(hipEventCreate(&rec.stop));
             QQ_HIP(hipEventRecord(rec.start, stream));
@@ -509,7 +510,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
         } else {
             QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
         }
-        if (g_prof) {
+        if (prof) {
             QQ_HIP(hipEventRecord(rec.stop, stream));
             rec.meta.kind = pp.nstates > 1 ? 2 : 1;
             rec.meta.pass_kind = (use_fast && pp.fkind >= 0) ? pp.fkind : -1;
@@ -537,13 +538,13 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
     for (const auto &pp : plan.passes)
         for (int o : pp.slot_out) fa.slot_out[s++] = (uint16_t)o;
     ProfRec rec{};
-    if (g_prof) {
+    if (prof) {
         QQ_HIP(hipEventCreate(&rec.start));
         QQ_HIP(hipEventCreate(&rec.stop));
         QQ_HIP(hipEventRecord(rec.start, stream));
     }
     QQ_HIP(launch_finalize(fa, stream));
-    if (g_prof) {
+    if (prof) {
         QQ_HIP(hipEventRecord(rec.stop, stream));
         rec.meta.kind = 3;
         rec.meta.pass_kind = -1;
@@ -606,14 +607,82 @@ struct ManyLayout {
     size_t params = 0, out = 0, total = 0;
 };
 
+// ---- graph-captured optimisation steps ------------------------------------------------------
+}  // namespace
+
+struct qq_graph {
+    qq_problem *pb = nullptr;
+    int p = 0, B = 0, flags = 0, device = 0;
+    Plan plan;
+    Layout L;
+    double lr = 0.01, beta1 = 0.9, beta2 = 0.999, eps = 1e-8;
+    double *x = nullptr;  // caller's device parameters [B][2p]
+    void *mem = nullptr;  // workspace, moments, outputs, counter (one allocation)
+    char *ws = nullptr;
+    double *m = nullptr, *v = nullptr, *energy = nullptr, *grad = nullptr, *hist = nullptr;
+    int *step = nullptr;
+    int hist_len = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~qq_graph()
+    {
+        (void)hipSetDevice(device);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+namespace {
+
+// One optimisation step on `stream`: the evaluation's pass and finalize kernels, then Adam.
+qq_status enqueue_step(qq_graph *g, hipStream_t stream, bool capturing)
+{
+    if (qq_status st = run_plan(g->pb, g->plan, g->L, g->p, g->B, g->flags, g->ws, g->x, stream, capturing);
+        st != QQ_OK)
+        return st;
+    AdamArgs a;
+    a.B = g->B;
+    a.p = g->p;
+    a.lr = g->lr;
+    a.beta1 = g->beta1;
+    a.beta2 = g->beta2;
+    a.eps = g->eps;
+    a.result = reinterpret_cast<const double *>(g->ws + g->L.out);
+    a.x = g->x;
+    a.m = g->m;
+    a.v = g->v;
+    a.step = g->step;
+    a.energy_out = g->energy;
+    a.grad_out = g->grad;
+    a.history = g->hist;
+    a.history_len = g->hist_len;
+    QQ_HIP(launch_adam(a, stream));
+    return QQ_OK;
+}
+
+qq_status zero_state(qq_graph *g, hipStream_t stream)
+{
+    const size_t np = (size_t)g->B * 2 * g->p;
+    QQ_HIP(launch_fill_f64(g->m, 0.0, np, stream));
+    QQ_HIP(launch_fill_f64(g->v, 0.0, np, stream));
+    QQ_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(g->step), 0u, 1, stream));
+    return QQ_OK;
+}
+
 constexpr double kDefaultWaitMs = 2000.0;
 
 int many_tiles_per_chunk(uint64_t tiles, const qq_many_options *opt)
 {
-    if (opt && opt->tiles_per_chunk > 0) return (int)std::min<uint64_t>((uint64_t)opt->tiles_per_chunk, tiles);
-    // about 256 chunks per pass: enough items per level to fill the device, few enough
-    // that per-item overhead stays small
-    return (int)std::max<uint64_t>(1, tiles / 256);
+    // 16 tiles (512 KiB of one complex64 state) per item: each item ends with an XCD-wide
+    // cache write-back and two device-scope atomics, which a 16-tile item amortises,
+    // while a 2^22-amplitude pass still splits into 64 items (measured on MI355X with
+    // the 512-problem uneven batch: 1 tile 107 ms, 8 tiles 30 ms, 16 and 32 tiles 25 ms)
+    const uint64_t want = (opt && opt->tiles_per_chunk > 0) ? (uint64_t)opt->tiles_per_chunk : 16;
+    return (int)std::min<uint64_t>(want, tiles);
 }
 
 qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *batch, int flags,
@@ -1385,6 +1454,129 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
             }
         }
     }
+    return QQ_OK;
+}
+
+qq_status qq_graph_create(qq_problem *pb, int p, int batch, int flags, const double *adam, double *params,
+                          int history, void *stream_, qq_graph **out)
+{
+    g_err.clear();
+    if (!out) return fail(QQ_E_INVALID, "out is NULL");
+    if (!params) return fail(QQ_E_INVALID, "params is NULL (device [batch][2p] parameters)");
+    if (flags & (QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE))
+        return fail(QQ_E_INVALID, "qq_graph_create takes device parameters implicitly; pass no *_ON_DEVICE flag");
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    if (history < 0) return fail(QQ_E_INVALID, "history = %d must be >= 0", history);
+    double hp[4] = {0.01, 0.9, 0.999, 1e-8};
+    if (adam) {
+        for (int i = 0; i < 4; ++i) hp[i] = adam[i];
+        if (!(hp[0] > 0.0 && std::isfinite(hp[0])) || !(hp[1] >= 0.0 && hp[1] < 1.0) || !(hp[2] >= 0.0 && hp[2] < 1.0) ||
+            !(hp[3] > 0.0 && std::isfinite(hp[3])))
+            return fail(QQ_E_INVALID, "Adam hyperparameters need lr > 0, 0 <= beta1, beta2 < 1, eps > 0");
+    }
+    std::unique_ptr<qq_graph> g(new (std::nothrow) qq_graph());
+    if (!g) return fail(QQ_E_NOMEM, "host allocation failed");
+    g->pb = pb;
+    g->p = p;
+    g->B = batch;
+    g->flags = (flags | QQ_ENERGY | QQ_GRAD | QQ_PARAMS_ON_DEVICE) & ~QQ_OUT_ON_DEVICE;
+    g->device = pb->device;
+    g->lr = hp[0];
+    g->beta1 = hp[1];
+    g->beta2 = hp[2];
+    g->eps = hp[3];
+    g->x = params;
+    g->hist_len = history;
+    g->plan = make_plan(pb->n, p, plan_mode(g->flags, false));
+    g->L = make_layout(pb, p, batch, g->flags, g->plan);
+    if (g->plan.nslots > kMaxSlots) return fail(QQ_E_UNSUPPORTED, "plan needs %d accumulator slots", g->plan.nslots);
+    const size_t np = (size_t)batch * 2 * p;
+    const size_t o_m = align_up(g->L.total), o_v = o_m + align_up(np * 8), o_e = o_v + align_up(np * 8),
+                 o_g = o_e + align_up((size_t)batch * 8), o_h = o_g + align_up(np * 8),
+                 o_s = o_h + align_up((size_t)std::max(1, history) * batch * 8), total = o_s + 256;
+    QQ_HIP(hipSetDevice(g->device));
+    if (qq_status st = check_device_fits(g->device, total, "the optimiser workspace"); st != QQ_OK) return st;
+    if (hipMalloc(&g->mem, total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) failed", total);
+    char *base = static_cast<char *>(g->mem);
+    g->ws = base;
+    g->m = reinterpret_cast<double *>(base + o_m);
+    g->v = reinterpret_cast<double *>(base + o_v);
+    g->energy = reinterpret_cast<double *>(base + o_e);
+    g->grad = reinterpret_cast<double *>(base + o_g);
+    g->hist = history > 0 ? reinterpret_cast<double *>(base + o_h) : nullptr;
+    g->step = reinterpret_cast<int *>(base + o_s);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if (qq_status st = zero_state(g.get(), stream); st != QQ_OK) return st;
+    if (history > 0) QQ_HIP(launch_fill_f64(g->hist, 0.0, (size_t)history * batch, stream));
+    QQ_HIP(launch_fill_f64(g->energy, 0.0, (size_t)batch, stream));
+    QQ_HIP(launch_fill_f64(g->grad, 0.0, np, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    // capture one step on a private stream (default priority)
+    QQ_HIP(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    QQ_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    const qq_status st = enqueue_step(g.get(), g->cap, true);
+    const std::string err = g_err;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->cap, &graph);
+    g->graph = graph;
+    if (st != QQ_OK) return fail(st, "capturing the step failed: %s", err.c_str());
+    if (ec != hipSuccess) return fail(QQ_E_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    QQ_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    *out = g.release();
+    return QQ_OK;
+}
+
+qq_status qq_graph_run(qq_graph *g, int steps, void *stream_)
+{
+    g_err.clear();
+    if (!g) return fail(QQ_E_INVALID, "graph is NULL");
+    if (steps < 0) return fail(QQ_E_INVALID, "steps = %d must be >= 0", steps);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(g->device));
+    for (int i = 0; i < steps; ++i) QQ_HIP(hipGraphLaunch(g->exec, stream));
+    return QQ_OK;
+}
+
+qq_status qq_graph_step_eager(qq_graph *g, void *stream_)
+{
+    g_err.clear();
+    if (!g) return fail(QQ_E_INVALID, "graph is NULL");
+    QQ_HIP(hipSetDevice(g->device));
+    return enqueue_step(g, static_cast<hipStream_t>(stream_), false);
+}
+
+qq_status qq_graph_reset(qq_graph *g, void *stream_)
+{
+    g_err.clear();
+    if (!g) return fail(QQ_E_INVALID, "graph is NULL");
+    QQ_HIP(hipSetDevice(g->device));
+    return zero_state(g, static_cast<hipStream_t>(stream_));
+}
+
+qq_status qq_graph_read(qq_graph *g, double *energy, double *grad, double *history, int *steps, int flags,
+                        void *stream_)
+{
+    g_err.clear();
+    if (!g) return fail(QQ_E_INVALID, "graph is NULL");
+    if (flags & ~QQ_OUT_ON_DEVICE) return fail(QQ_E_INVALID, "only QQ_OUT_ON_DEVICE is accepted");
+    if (history && g->hist_len == 0) return fail(QQ_E_INVALID, "the graph keeps no history (created with history = 0)");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(g->device));
+    const hipMemcpyKind kind = (flags & QQ_OUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t np = (size_t)g->B * 2 * g->p;
+    if (energy) QQ_HIP(hipMemcpyAsync(energy, g->energy, (size_t)g->B * 8, kind, stream));
+    if (grad) QQ_HIP(hipMemcpyAsync(grad, g->grad, np * 8, kind, stream));
+    if (history) QQ_HIP(hipMemcpyAsync(history, g->hist, (size_t)g->hist_len * g->B * 8, kind, stream));
+    int hs = 0;
+    if (steps) QQ_HIP(hipMemcpyAsync(&hs, g->step, sizeof(int), hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    if (steps) *steps = hs;
+    return QQ_OK;
+}
+
+qq_status qq_graph_destroy(qq_graph *g)
+{
+    delete g;
     return QQ_OK;
 }
 

@@ -191,6 +191,22 @@ struct ManyArgs {
 hipError_t launch_many(const ManyArgs &a, int diag_type, int max_grid, hipStream_t s, int *grid_out);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 
+// Device Adam step (qq_optim.hip).
+struct AdamArgs {
+    int B, p;
+    double lr, beta1, beta2, eps;
+    const double *result;  // [B][1 + 2p]: energy, then the interleaved gradient
+    double *x;             // [B][2p] parameters, updated in place
+    double *m, *v;         // [B][2p] moments
+    int *step;             // completed steps (device)
+    double *energy_out;    // [B] energy of the step (at the parameters before the update)
+    double *grad_out;      // [B][2p] gradient of the step, or NULL
+    double *history;       // [history_len][B] energies by step (ring), or NULL
+    int history_len;
+};
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+
 // Plain complex128 per-gate path (qq_plain.hip).
 struct PlainArgs {
     int n;

@@ -15,9 +15,12 @@
 // a wait that runs out sets an error flag, after which every workgroup stops
 // taking items and the launch ends (the host reports the error).
 //
-// Memory ordering.  Each XCD has its own L2, so completion uses agent-scope
-// release (every thread, after its stores) before the counter increment, and a
-// waiting workgroup uses agent-scope acquire after the counter is seen.
+// Memory ordering.  Each XCD has its own L2, so an item is published with an
+// agent-scope release (L2 write-back) before its counter increment, and a waiting
+// workgroup takes an agent-scope acquire (L2 and vector-cache invalidate) once the
+// counter is reached.  Both are XCD-wide cache operations, so each is issued once
+// per item by thread 0, the other waves being ordered through the workgroup barrier
+// after their own stores have completed.
 //
 // Reductions.  Each item writes its workgroup's FP64 partial sums to a slot of
 // its own; the workgroup that completes the last item of a state sums the
@@ -333,13 +336,15 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
                     }
                     __builtin_amdgcn_s_sleep(2);
                 }
+                // acquire for the whole workgroup: the invalidate covers the CU's vector
+                // cache, which the other waves share, and they load only after the barrier
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 s_msg[1] = ok;
             }
             __syncthreads();
             const uint32_t ok = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_msg[1]);
             __syncthreads();
             if (!ok) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
 
         const ManyPass &P = A.pass[I.pass_off + (int)sg.pass];
@@ -355,8 +360,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
             run_chunk<DT>(I, P, A.partial, lds, s_red, ti, b, chunk);
         }
 
-        // publish: every thread's stores, then one increment of the state's counter
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // publish: every wave waits for its own stores to complete (to the XCD's L2), the
+        // barrier orders them before thread 0, whose agent-scope release writes the L2
+        // back before the counter increment; one release per item instead of one per wave
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (t == 0) {
             const uint32_t done = __hip_atomic_fetch_add(cnt + state, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
@@ -365,10 +372,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
         __syncthreads();
         const uint32_t last = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_msg[0]);
         __syncthreads();
-        if (last) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            finish_state(A, I, b, t);
-        }
+        if (last) finish_state(A, I, b, t);  // thread 0's acq_rel increment acquired for the CU
     }
 }
 

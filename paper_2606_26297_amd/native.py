@@ -93,6 +93,12 @@ SIGNATURES = {
     "qq_workspace_size_many": ([_int, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), _szp], _int),
     "qq_evaluate_many": ([_int, _vp, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), _vp, ctypes.c_size_t, _vp,
                           _vp, _vp], _int),
+    "qq_graph_create": ([_vp, _int, _int, _int, _dp, _vp, _int, _vp, ctypes.POINTER(_vp)], _int),
+    "qq_graph_run": ([_vp, _int, _vp], _int),
+    "qq_graph_step_eager": ([_vp, _vp], _int),
+    "qq_graph_reset": ([_vp, _vp], _int),
+    "qq_graph_read": ([_vp, _vp, _vp, _vp, ctypes.POINTER(_int), _int, _vp], _int),
+    "qq_graph_destroy": ([_vp], _int),
     "qq_profile_enable": ([_int], _int),
     "qq_profile_read": ([ctypes.c_void_p, _int, ctypes.POINTER(_int)], _int),
 }
@@ -317,6 +323,48 @@ def qq_evaluate_many(handles, p, batch, params, flags, opt, workspace, ws_bytes,
                                   ctypes.cast(pp, _vp), int(flags), _many_options(opt), wp, int(ws_bytes),
                                   _stream_ptr(stream), ctypes.cast(ep, _vp),
                                   ctypes.cast(gp, _vp) if grad_out is not None else None))
+
+
+def qq_graph_create(handle, p, batch, flags, adam, params, history=0, stream=None):
+    """params: device tensor [batch, 2p] float64 (updated in place by every step)."""
+    hp = None
+    if adam is not None:
+        a = _f64(adam)
+        if a.shape != (4,):
+            raise ValueError("adam = (lr, beta1, beta2, eps)")
+        hp = _ptr(a)
+    out = _vp()
+    _check(lib().qq_graph_create(handle, int(p), int(batch), int(flags), hp, _dev_ptr(params), int(history),
+                                 _stream_ptr(stream), ctypes.byref(out)))
+    return out
+
+
+def qq_graph_run(graph, steps, stream=None):
+    _check(lib().qq_graph_run(graph, int(steps), _stream_ptr(stream)))
+
+
+def qq_graph_step_eager(graph, stream=None):
+    _check(lib().qq_graph_step_eager(graph, _stream_ptr(stream)))
+
+
+def qq_graph_reset(graph, stream=None):
+    _check(lib().qq_graph_reset(graph, _stream_ptr(stream)))
+
+
+def qq_graph_read(graph, batch, p, history=0, stream=None):
+    """(energy[batch], grad[batch, 2p], history[history, batch] or None, steps) as host arrays."""
+    e = np.empty(batch)
+    g = np.empty((batch, 2 * p))
+    h = np.empty((history, batch)) if history > 0 else None
+    st = _int(0)
+    _check(lib().qq_graph_read(graph, e.ctypes.data_as(_vp), g.ctypes.data_as(_vp),
+                               h.ctypes.data_as(_vp) if h is not None else None, ctypes.byref(st), 0,
+                               _stream_ptr(stream)))
+    return e, g, h, st.value
+
+
+def qq_graph_destroy(graph):
+    _check(lib().qq_graph_destroy(graph))
 
 
 def qq_profile_enable(enable: bool):

@@ -1,0 +1,156 @@
+"""GPU tests of the graph-captured optimisation step [energy + gradient -> device Adam].
+
+Every replay of the captured graph is compared bit for bit with the same step
+launched eagerly (qq_graph_step_eager) on an identical copy of the parameters,
+with other eager GPU work and host synchronisations between the replays.  The
+Adam update itself is checked against a float64 numpy Adam fed with the
+gradients of qq_evaluate (1e-12 relative), and the loop is checked to lower the
+energy.
+"""
+import numpy as np
+import pytest
+
+from paper_2606_26297_amd import native as N
+from paper_2606_26297_amd import workloads as W
+from paper_2606_26297_amd.qaoa import Problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    N.lib()
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+CASES = [("regular3_n10_single_pass", 10, 2, 4, 0), ("regular3_n16_two_sets", 16, 3, 4, 0),
+         ("regular3_n22_partial_set", 22, 2, 2, 0), ("regular3_n12_c128", 12, 2, 2, N.QQ_C128)]
+
+
+@pytest.mark.parametrize("name,n,p,B,flags", CASES, ids=[c[0] for c in CASES])
+def test_graph_replays_match_eager_steps(name, n, p, B, flags):
+    import torch
+
+    inst = W.regular_graph_qubo(n, 11)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    x0 = W.random_params(p, B, 12)
+    xg = torch.tensor(x0, device="cuda:0")
+    xe = torch.tensor(x0, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    gg = N.qq_graph_create(pb.handle, p, B, flags, None, xg, 8, stream)
+    ge = N.qq_graph_create(pb.handle, p, B, flags, None, xe, 8, stream)
+    try:
+        for k in range(1, 5):
+            N.qq_graph_run(gg, 1, stream)
+            torch.cuda.synchronize()
+            # the program's own eager work between replays
+            N.qq_graph_step_eager(ge, stream)
+            junk = torch.randn(1 << 16, device="cuda:0").sum()
+            pb.evaluate(x0[:1], grad=True)
+            torch.cuda.synchronize()
+            assert float(junk) == float(junk)
+            assert torch.equal(xg, xe), (name, k)
+            eg, dg, hg, sg = N.qq_graph_read(gg, B, p, 8, stream)
+            ee, de, he, se = N.qq_graph_read(ge, B, p, 8, stream)
+            assert sg == se == k
+            assert np.array_equal(eg, ee) and np.array_equal(dg, de) and np.array_equal(hg, he)
+        # several replays in one call
+        N.qq_graph_run(gg, 3, stream)
+        for _ in range(3):
+            N.qq_graph_step_eager(ge, stream)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe)
+        assert N.qq_graph_read(gg, B, p, 8, stream)[3] == 7
+    finally:
+        N.qq_graph_destroy(gg)
+        N.qq_graph_destroy(ge)
+
+
+def adam_ref(x, g, m, v, t, lr=0.01, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    x = x - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    return x, m, v
+
+
+def test_adam_update_matches_numpy_with_evaluate_gradients():
+    import torch
+
+    inst = W.regular_graph_qubo(14, 21)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    p, B = 3, 3
+    x = W.random_params(p, B, 22)
+    xt = torch.tensor(x, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    hp = (0.05, 0.8, 0.99, 1e-6)
+    g = N.qq_graph_create(pb.handle, p, B, 0, hp, xt, 4, stream)
+    m = np.zeros_like(x)
+    v = np.zeros_like(x)
+    try:
+        for t in range(1, 4):
+            e_ref, g_ref = pb.evaluate(x, grad=True)  # same kernels, deterministic
+            N.qq_graph_run(g, 1, stream)
+            torch.cuda.synchronize()
+            e, gr, hist, steps = N.qq_graph_read(g, B, p, 4, stream)
+            assert steps == t
+            assert np.array_equal(e, e_ref) and np.array_equal(gr, g_ref)
+            assert np.array_equal(hist[t - 1], e_ref)
+            x, m, v = adam_ref(x, g_ref, m, v, t, *hp)
+            assert np.max(np.abs(xt.cpu().numpy() - x)) <= 1e-12 * np.max(np.abs(x))
+    finally:
+        N.qq_graph_destroy(g)
+
+
+def test_graph_loop_lowers_the_energy_and_reset_restarts():
+    import torch
+
+    inst = W.regular_graph_qubo(12, 31)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    p, B, steps = 2, 8, 60
+    x0 = W.random_params(p, B, 32)
+    xt = torch.tensor(x0, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    g = N.qq_graph_create(pb.handle, p, B, 0, (0.02, 0.9, 0.999, 1e-8), xt, steps, stream)
+    try:
+        N.qq_graph_run(g, steps, stream)
+        e, _, hist, n = N.qq_graph_read(g, B, p, steps, stream)
+        assert n == steps
+        assert np.all(hist[-1] < hist[0])
+        e_end = pb.evaluate(xt.cpu().numpy())
+        assert np.all(e_end < hist[0])
+        N.qq_graph_reset(g, stream)
+        xt.copy_(torch.tensor(x0, device="cuda:0"))
+        N.qq_graph_run(g, 1, stream)
+        e1, _, _, n1 = N.qq_graph_read(g, B, p, steps, stream)
+        assert n1 == 1 and np.array_equal(e1, hist[0])
+    finally:
+        N.qq_graph_destroy(g)
+
+
+def test_graph_validation():
+    import torch
+
+    inst = W.regular_graph_qubo(10, 41)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    xt = torch.zeros(2, 4, dtype=torch.float64, device="cuda:0")
+    for bad in [(0.0, 0.9, 0.999, 1e-8), (0.01, 1.0, 0.999, 1e-8), (0.01, 0.9, 0.999, 0.0)]:
+        with pytest.raises(N.QQError) as ei:
+            N.qq_graph_create(pb.handle, 2, 2, 0, bad, xt)
+        assert ei.value.status == N.QQ_E_INVALID
+    with pytest.raises(N.QQError) as ei:
+        N.qq_graph_create(pb.handle, 2, 2, N.QQ_OUT_ON_DEVICE, None, xt)
+    assert ei.value.status == N.QQ_E_INVALID
+    with pytest.raises(N.QQError) as ei:
+        N.qq_graph_create(pb.handle, 2, 2, N.QQ_PARTITIONED, None, xt)
+    assert ei.value.status == N.QQ_E_ALLOCATION
+    g = N.qq_graph_create(pb.handle, 2, 2, 0, None, xt, 0)
+    try:
+        with pytest.raises(N.QQError) as ei:
+            N.qq_graph_read(g, 2, 2, history=3)
+        assert ei.value.status == N.QQ_E_INVALID
+        with pytest.raises(N.QQError):
+            N.qq_graph_run(g, -1)
+    finally:
+        N.qq_graph_destroy(g)
