@@ -229,6 +229,49 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
                            size_t ws_bytes, void *stream, double *const *energy_out, double *const *grad_out);
 
 /*
+ * Schedules and the autotuner (circuit-reuse section: work prepared once per
+ * problem and settings and reused; here the launch schedule).
+ *
+ * A schedule fixes, for one (p, batch, flags) of a problem:
+ *   workgroups_per_state  G: workgroups that share one state in every pass
+ *                         (power of two, 1 <= G <= 2^(n-12)); default
+ *                         min(2^(n-12), 4096 / batch) rounded down to a power of two
+ *   set_pairing           which 4-qubit runs above qubit 11 share a high pass when
+ *                         n - 12 is a multiple of 8 with at least four runs
+ *                         (0: run i with run m-1-i, 1: adjacent runs, 2: run i with
+ *                         run i + m/2); otherwise only 0
+ * Results do not depend on the schedule beyond the order of FP64 partial sums.
+ * qq_set_schedule pins one (NULL restores the default); qq_get_schedule reports
+ * the one in force.  qq_workspace_size, qq_evaluate and qq_graph_create use it.
+ *
+ * qq_autotune times every candidate (G of the default, half and double it,
+ * times every pairing that applies) with HIP events on seeded parameter sets
+ * (one warm-up, median of three), pins the fastest and, if cache_path is not
+ * NULL, appends it to that JSON-lines file; an entry already there for the same
+ * device, n, p, batch, planning flags and diagonal width is used without timing.
+ * qq_autotune_many does the same for qq_evaluate_many over tiles_per_chunk in
+ * {4, 8, 16, 32, 64} and max_workgroups in {0, 2 x compute units}, keyed by a
+ * hash of every problem's (n, p, batch, diagonal width); it returns the options
+ * (to pass to qq_evaluate_many) and the measured time in ms_out (may be NULL).
+ * Both allocate their own device memory and synchronise `stream`.
+ */
+typedef struct {
+    int workgroups_per_state;
+    int set_pairing;
+    double ms;        /* timed duration of one evaluation (autotune), else as pinned */
+    int pinned;       /* 1 when a schedule is pinned for the key */
+    int from_cache;   /* 1 when qq_autotune read it from the cache file */
+    int tried;        /* candidates timed by qq_autotune */
+} qq_schedule;
+
+qq_status qq_set_schedule(qq_problem *prob, int p, int batch, int flags, const qq_schedule *schedule);
+qq_status qq_get_schedule(const qq_problem *prob, int p, int batch, int flags, qq_schedule *out);
+qq_status qq_autotune(qq_problem *prob, int p, int batch, int flags, const char *cache_path, void *stream,
+                      qq_schedule *out);
+qq_status qq_autotune_many(int count, qq_problem *const *problems, const int *p, const int *batch, int flags,
+                           const char *cache_path, void *stream, qq_many_options *out, double *ms_out);
+
+/*
  * Optimisation steps [energy + gradient -> Adam] captured once in a HIP graph
  * and replayed (optimisation-overhead section: Adam with a cheaper gradient,
  * here the exact adjoint one; throughput subsection: parallel multi-start runs,

@@ -105,6 +105,12 @@ struct qq_problem {
     void *d_tables = nullptr;
     void *d_cross = nullptr;
     PartDesc *d_part = nullptr;
+    // schedules pinned by qq_set_schedule / qq_autotune, keyed by (p, batch, planning flags)
+    struct Sched {
+        int p, batch, flags, G, pairing;
+        double ms;
+    };
+    std::vector<Sched> sched;
 
     ~qq_problem()
     {
@@ -129,12 +135,17 @@ struct SetDesc {
 };
 
 // High-set layout.  When the qubits above 11 split into full sets (n - 12 a
-// multiple of 8) they are cut into 4-qubit runs R_0..R_{m-1} and run i is paired
-// with run m-1-i: the pairing measured fastest on MI355X, since it spreads the
-// qubits of the largest address strides over both high sets.  Otherwise each
-// set is a contiguous 8-qubit window [h, h+8), the last one shifted down to end
-// at n with its already-covered qubits inactive.
-std::vector<SetDesc> make_sets(int n)
+// multiple of 8) they are cut into 4-qubit runs R_0..R_{m-1}, paired per
+// `pairing`: 0 pairs run i with run m-1-i (the default, measured fastest on
+// MI355X at n = 28: it spreads the qubits of the largest address strides over
+// both high sets), 1 pairs adjacent runs (2i, 2i+1), 2 pairs run i with run
+// i + m/2.  Otherwise each set is a contiguous 8-qubit window [h, h+8), the last
+// one shifted down to end at n with its already-covered qubits inactive.
+constexpr int kPairings = 3;
+
+bool pairing_applies(int n) { return n > kTileBits && (n - kTileBits) % 8 == 0 && (n - kTileBits) / 4 >= 4; }
+
+std::vector<SetDesc> make_sets(int n, int pairing = 0)
 {
     std::vector<SetDesc> sets;
     if (n <= kTileBits) {
@@ -144,7 +155,11 @@ std::vector<SetDesc> make_sets(int n)
     sets.push_back({0, 4, 8, 0x0fff});
     if ((n - kTileBits) % 8 == 0) {
         const int m = (n - kTileBits) / 4;
-        for (int i = 0; i < m / 2; ++i) sets.push_back({1, kTileBits + 4 * i, kTileBits + 4 * (m - 1 - i), 0x0ff0});
+        for (int i = 0; i < m / 2; ++i) {
+            const int a = pairing == 1 ? 2 * i : i;
+            const int c = pairing == 1 ? 2 * i + 1 : pairing == 2 ? i + m / 2 : m - 1 - i;
+            sets.push_back({1, kTileBits + 4 * a, kTileBits + 4 * c, 0x0ff0});
+        }
         return sets;
     }
     for (int q0 = kTileBits; q0 < n; q0 += 8) {
@@ -227,10 +242,10 @@ Op op_acc(PassPlan &pp, uint8_t kind, int k, int out, uint8_t flags)
 // layer k on the set, applies phase k+1 and mixes layer k+1 on the same set.
 // A forward evaluation with s sets takes 1 + p(s-1) passes.  The adjoint
 // sweep runs the same zig-zag backwards over (psi, lambda).
-Plan make_plan(int n, int p, int mode)
+Plan make_plan(int n, int p, int mode, int pairing = 0)
 {
     Plan plan;
-    plan.sets = make_sets(n);
+    plan.sets = make_sets(n, pairing);
     const int s = (int)plan.sets.size();
     const bool grad = mode & PM_GRAD, energy = mode & (PM_ENERGY | PM_GRAD), store = mode & PM_STORE,
                part = mode & PM_PART;
@@ -359,14 +374,14 @@ struct Layout {
     int nslots = 0;
 };
 
-Layout make_layout(const qq_problem *pb, int p, int B, int flags, const Plan &plan)
+Layout make_layout(const qq_problem *pb, int p, int B, int flags, const Plan &plan, int G = 0)
 {
     Layout L;
     const size_t es = (flags & QQ_C128) ? 16 : 8;
     const size_t state = (size_t)pb->dim * es * (size_t)B;
     const bool grad = flags & QQ_GRAD;
     const bool multi = plan.sets.size() > 1;
-    L.G = choose_G(pb->n, B);
+    L.G = G > 0 ? G : choose_G(pb->n, B);
     L.nslots = plan.nslots;
     size_t off = 0;
     L.psi = off;
@@ -391,6 +406,29 @@ int plan_mode(int flags, bool store)
     if (flags & QQ_PARTITIONED) m |= PM_PART;
     if (store) m |= PM_STORE;
     return m;
+}
+
+// Flags that change the plan or the layout (the energy is always computed).
+int sched_flags(int flags) { return flags & (QQ_GRAD | QQ_PARTITIONED | QQ_C128); }
+
+const qq_problem::Sched *find_sched(const qq_problem *pb, int p, int batch, int flags)
+{
+    for (const auto &e : pb->sched)
+        if (e.p == p && e.batch == batch && e.flags == sched_flags(flags)) return &e;
+    return nullptr;
+}
+
+// Plan and layout of an evaluation, under the problem's pinned schedule if any.
+Plan plan_for(const qq_problem *pb, int p, int batch, int flags, bool store)
+{
+    const auto *e = find_sched(pb, p, batch, flags);
+    return make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, store), e ? e->pairing : 0);
+}
+
+Layout layout_for(const qq_problem *pb, int p, int batch, int flags, const Plan &plan)
+{
+    const auto *e = find_sched(pb, p, batch, flags);
+    return make_layout(pb, p, batch, flags, plan, e ? e->G : 0);
 }
 
 qq_status check_params_host(const double *params, size_t count)
@@ -674,6 +712,120 @@ qq_status zero_state(qq_graph *g, hipStream_t stream)
 }
 
 constexpr double kDefaultWaitMs = 2000.0;
+
+// ---- autotuning -----------------------------------------------------------------------------
+// Candidates are timed with HIP events (one warm-up, then the median of three
+// runs) on seeded parameter sets; the best is pinned in the problem handle and,
+// given a cache path, appended to a JSON-lines file that later calls read
+// before timing anything.
+std::string device_tag(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string t = std::string(prop.name) + "|" + prop.gcnArchName;
+    for (char &c : t)
+        if (c == '"' || c == '\\' || c == '\n') c = '_';
+    return t;
+}
+
+// Seeded parameters in [0, pi) (a 64-bit LCG; the values only need to be typical).
+std::vector<double> tune_params(size_t count, uint64_t seed)
+{
+    std::vector<double> x(count);
+    uint64_t st = seed * 6364136223846793005ull + 1442695040888963407ull;
+    for (double &v : x) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        v = (double)(st >> 11) * (3.141592653589793 / 9007199254740992.0);
+    }
+    return x;
+}
+
+// The value of "key": in a cache line (numbers only), or false.
+bool json_num(const std::string &line, const char *key, double &out)
+{
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = line.find(k);
+    if (at == std::string::npos) return false;
+    return std::sscanf(line.c_str() + at + k.size(), "%lf", &out) == 1;
+}
+
+bool cache_lookup(const char *path, const std::string &key, std::string &line_out)
+{
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char buf[1024];
+    bool found = false;
+    while (std::fgets(buf, sizeof buf, f)) {
+        const std::string line(buf);
+        if (line.compare(0, key.size(), key) == 0) {
+            line_out = line;  // the last matching entry wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+qq_status cache_append(const char *path, const std::string &line)
+{
+    if (!path) return QQ_OK;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return fail(QQ_E_INVALID, "cannot open the tuning cache %s for appending", path);
+    std::fputs(line.c_str(), f);
+    std::fputc('\n', f);
+    std::fclose(f);
+    return QQ_OK;
+}
+
+// Median of three timed runs of `run` after one warm-up, in ms.
+template <typename F>
+qq_status time_median(hipStream_t stream, F run, double &ms)
+{
+    if (qq_status st = run(); st != QQ_OK) return st;
+    hipEvent_t a, b;
+    QQ_HIP(hipEventCreate(&a));
+    QQ_HIP(hipEventCreate(&b));
+    double t[3];
+    qq_status st = QQ_OK;
+    for (int r = 0; r < 3 && st == QQ_OK; ++r) {
+        float f = 0.0f;
+        if (hipEventRecord(a, stream) != hipSuccess) st = fail(QQ_E_DEVICE, "hipEventRecord failed");
+        if (st == QQ_OK) st = run();
+        if (st == QQ_OK && (hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                            hipEventElapsedTime(&f, a, b) != hipSuccess))
+            st = fail(QQ_E_DEVICE, "event timing failed");
+        t[r] = f;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != QQ_OK) return st;
+    std::sort(t, t + 3);
+    ms = t[1];
+    return QQ_OK;
+}
+
+void pin_sched(qq_problem *pb, int p, int batch, int flags, int G, int pairing, double ms)
+{
+    const int sf = sched_flags(flags);
+    for (auto &e : pb->sched)
+        if (e.p == p && e.batch == batch && e.flags == sf) {
+            e.G = G;
+            e.pairing = pairing;
+            e.ms = ms;
+            return;
+        }
+    pb->sched.push_back({p, batch, sf, G, pairing, ms});
+}
+
+uint64_t fnv1a(uint64_t h, int64_t v)
+{
+    for (int i = 0; i < 8; ++i) {
+        h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+        h *= 1099511628211ull;
+    }
+    return h;
+}
 
 int many_tiles_per_chunk(uint64_t tiles, const qq_many_options *opt)
 {
@@ -1167,8 +1319,8 @@ qq_status qq_workspace_size(const qq_problem *pb, int p, int batch, int flags, s
 {
     if (!bytes) return fail(QQ_E_INVALID, "bytes is NULL");
     if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
-    const Plan plan = make_plan(pb->n, p, plan_mode(flags, false));
-    *bytes = make_layout(pb, p, batch, flags, plan).total;
+    const Plan plan = plan_for(pb, p, batch, flags, false);
+    *bytes = layout_for(pb, p, batch, flags, plan).total;
     return QQ_OK;
 }
 
@@ -1182,8 +1334,8 @@ qq_status qq_evaluate(qq_problem *pb, int p, int batch, const double *params, in
     if ((flags & QQ_GRAD) && !grad_out) return fail(QQ_E_INVALID, "QQ_GRAD requires grad_out");
     if (!(flags & QQ_PARAMS_ON_DEVICE))
         if (qq_status st = check_params_host(params, (size_t)batch * 2 * p); st != QQ_OK) return st;
-    const Plan plan = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false));
-    const Layout L = make_layout(pb, p, batch, flags, plan);
+    const Plan plan = plan_for(pb, p, batch, flags, false);
+    const Layout L = layout_for(pb, p, batch, flags, plan);
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     QQ_HIP(hipSetDevice(pb->device));
     DevBuf own;
@@ -1228,8 +1380,8 @@ static qq_status state_into(qq_problem *pb, int p, const double *params, int fla
     if (!(flags & QQ_PARAMS_ON_DEVICE))
         if (qq_status st = check_params_host(params, 2 * (size_t)p); st != QQ_OK) return st;
     const int f = (flags & ~QQ_GRAD) | QQ_ENERGY;
-    const Plan plan = make_plan(pb->n, p, plan_mode(f, true));
-    L = make_layout(pb, p, 1, f, plan);
+    const Plan plan = plan_for(pb, p, 1, f, true);
+    L = layout_for(pb, p, 1, f, plan);
     QQ_HIP(hipSetDevice(pb->device));
     if (qq_status st = check_device_fits(pb->device, L.total, "the state"); st != QQ_OK) return st;
     if (hipMalloc(&own.p, L.total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) failed", L.total);
@@ -1487,8 +1639,8 @@ qq_status qq_graph_create(qq_problem *pb, int p, int batch, int flags, const dou
     g->eps = hp[3];
     g->x = params;
     g->hist_len = history;
-    g->plan = make_plan(pb->n, p, plan_mode(g->flags, false));
-    g->L = make_layout(pb, p, batch, g->flags, g->plan);
+    g->plan = plan_for(pb, p, batch, g->flags, false);
+    g->L = layout_for(pb, p, batch, g->flags, g->plan);
     if (g->plan.nslots > kMaxSlots) return fail(QQ_E_UNSUPPORTED, "plan needs %d accumulator slots", g->plan.nslots);
     const size_t np = (size_t)batch * 2 * p;
     const size_t o_m = align_up(g->L.total), o_v = o_m + align_up(np * 8), o_e = o_v + align_up(np * 8),
@@ -1577,6 +1729,218 @@ qq_status qq_graph_read(qq_graph *g, double *energy, double *grad, double *histo
 qq_status qq_graph_destroy(qq_graph *g)
 {
     delete g;
+    return QQ_OK;
+}
+
+qq_status qq_set_schedule(qq_problem *pb, int p, int batch, int flags, const qq_schedule *sch)
+{
+    g_err.clear();
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    if (!sch) {  // back to the built-in heuristic
+        const int sf = sched_flags(flags);
+        pb->sched.erase(std::remove_if(pb->sched.begin(), pb->sched.end(),
+                                       [&](const qq_problem::Sched &e) {
+                                           return e.p == p && e.batch == batch && e.flags == sf;
+                                       }),
+                        pb->sched.end());
+        return QQ_OK;
+    }
+    const uint64_t T = tiles_per_state(pb->n);
+    const int G = sch->workgroups_per_state;
+    if (G < 1 || (G & (G - 1)) || (uint64_t)G > T)
+        return fail(QQ_E_INVALID, "workgroups_per_state = %d must be a power of two in [1, %llu]", G,
+                    (unsigned long long)T);
+    if (sch->set_pairing < 0 || sch->set_pairing >= kPairings || (sch->set_pairing != 0 && !pairing_applies(pb->n)))
+        return fail(QQ_E_INVALID, "set_pairing = %d is not available at n = %d", sch->set_pairing, pb->n);
+    if ((size_t)batch * (size_t)G > 0x7fffffffull) return fail(QQ_E_INVALID, "batch * workgroups_per_state too large");
+    pin_sched(pb, p, batch, flags, G, sch->set_pairing, sch->ms);
+    return QQ_OK;
+}
+
+qq_status qq_get_schedule(const qq_problem *pb, int p, int batch, int flags, qq_schedule *out)
+{
+    g_err.clear();
+    if (!out) return fail(QQ_E_INVALID, "out is NULL");
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    std::memset(out, 0, sizeof *out);
+    if (const auto *e = find_sched(pb, p, batch, flags)) {
+        out->workgroups_per_state = e->G;
+        out->set_pairing = e->pairing;
+        out->ms = e->ms;
+        out->pinned = 1;
+    } else {
+        out->workgroups_per_state = choose_G(pb->n, batch);
+        out->set_pairing = 0;
+    }
+    return QQ_OK;
+}
+
+qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *cache_path, void *stream_,
+                      qq_schedule *out)
+{
+    g_err.clear();
+    if (!out) return fail(QQ_E_INVALID, "out is NULL");
+    flags &= ~(QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE);
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    std::memset(out, 0, sizeof *out);
+    char keybuf[512];
+    std::snprintf(keybuf, sizeof keybuf,
+                  "{\"kind\":\"evaluate\",\"device\":\"%s\",\"n\":%d,\"p\":%d,\"batch\":%d,\"flags\":%d,"
+                  "\"diag_bytes\":%d,",
+                  device_tag(pb->device).c_str(), pb->n, p, batch, sched_flags(flags), diag_bytes_of(pb->diag_type));
+    const std::string key(keybuf);
+    std::string line;
+    if (cache_lookup(cache_path, key, line)) {
+        double G = 0, pr = 0, ms = 0;
+        if (json_num(line, "G", G) && json_num(line, "pairing", pr) && json_num(line, "ms", ms)) {
+            qq_schedule s{(int)G, (int)pr, ms, 1, 1, 0};
+            if (qq_status st = qq_set_schedule(pb, p, batch, flags, &s); st == QQ_OK) {
+                *out = s;
+                return QQ_OK;
+            }
+            g_err.clear();  // a stale entry: tune again
+        }
+    }
+    // candidates: the heuristic G, half and double it; every pairing where it applies
+    const uint64_t T = tiles_per_state(pb->n);
+    const int G0 = choose_G(pb->n, batch);
+    std::vector<int> Gs;
+    for (int G : {G0 / 2, G0, G0 * 2})
+        if (G >= 1 && (uint64_t)G <= T && (size_t)batch * G <= 0x7fffffffull) Gs.push_back(G);
+    const int npair = pairing_applies(pb->n) ? kPairings : 1;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(pb->device));
+    size_t need = 0;
+    const Plan plan0 = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false), 0);
+    for (int G : Gs) need = std::max(need, make_layout(pb, p, batch, flags, plan0, G).total);
+    if (qq_status st = check_device_fits(pb->device, need, "the tuning workspace"); st != QQ_OK) return st;
+    DevBuf ws, dx;
+    if (hipMalloc(&ws.p, need) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) for tuning failed", need);
+    const std::vector<double> x = tune_params((size_t)batch * 2 * p, 0x5eed + (uint64_t)pb->n * 131 + p);
+    QQ_HIP(hipMalloc(&dx.p, x.size() * sizeof(double)));
+    QQ_HIP(hipMemcpy(dx.p, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice));
+    const int eflags = flags | QQ_PARAMS_ON_DEVICE;
+    double best = INFINITY;
+    int bestG = G0, bestP = 0, tried = 0;
+    for (int pr = 0; pr < npair; ++pr) {
+        const Plan plan = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false), pr);
+        for (int G : Gs) {
+            const Layout L = make_layout(pb, p, batch, flags, plan, G);
+            double ms = 0;
+            auto run = [&]() {
+                return run_plan(pb, plan, L, p, batch, eflags, static_cast<char *>(ws.p),
+                                static_cast<const double *>(dx.p), stream, true);
+            };
+            if (qq_status st = time_median(stream, run, ms); st != QQ_OK) return st;
+            ++tried;
+            if (ms < best) {
+                best = ms;
+                bestG = G;
+                bestP = pr;
+            }
+        }
+    }
+    pin_sched(pb, p, batch, flags, bestG, bestP, best);
+    char tail[160];
+    std::snprintf(tail, sizeof tail, "\"G\":%d,\"pairing\":%d,\"ms\":%.4f}", bestG, bestP, best);
+    if (qq_status st = cache_append(cache_path, key + tail); st != QQ_OK) return st;
+    *out = qq_schedule{bestG, bestP, best, 1, 0, tried};
+    return QQ_OK;
+}
+
+qq_status qq_autotune_many(int count, qq_problem *const *problems, const int *p, const int *batch, int flags,
+                           const char *cache_path, void *stream_, qq_many_options *out, double *ms_out)
+{
+    g_err.clear();
+    if (!out) return fail(QQ_E_INVALID, "out is NULL");
+    flags &= ~(QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE);
+    if (qq_status st = validate_many(count, problems, p, batch, flags); st != QQ_OK) return st;
+    uint64_t h = 1469598103934665603ull;
+    for (int i = 0; i < count; ++i) {
+        h = fnv1a(h, problems[i]->n);
+        h = fnv1a(h, p[i]);
+        h = fnv1a(h, batch[i]);
+        h = fnv1a(h, diag_bytes_of(problems[i]->diag_type));
+    }
+    const int device = problems[0]->device;
+    char keybuf[512];
+    std::snprintf(keybuf, sizeof keybuf, "{\"kind\":\"many\",\"device\":\"%s\",\"count\":%d,\"flags\":%d,\"shape\":\"%016llx\",",
+                  device_tag(device).c_str(), count, sched_flags(flags), (unsigned long long)h);
+    const std::string key(keybuf);
+    std::string line;
+    if (cache_lookup(cache_path, key, line)) {
+        double tpc = 0, mw = 0, ms = 0;
+        if (json_num(line, "tiles_per_chunk", tpc) && json_num(line, "max_workgroups", mw) && json_num(line, "ms", ms) &&
+            tpc >= 1 && mw >= 0) {
+            out->tiles_per_chunk = (int)tpc;
+            out->max_workgroups = (int)mw;
+            out->wait_limit_ms = 0.0;
+            if (ms_out) *ms_out = ms;
+            return QQ_OK;
+        }
+    }
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(device));
+    int cus = 0;
+    QQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    // parameters on the device, outputs on the device
+    std::vector<std::vector<double>> xs(count);
+    size_t np = 0, ne = 0;
+    for (int i = 0; i < count; ++i) {
+        xs[i] = tune_params((size_t)batch[i] * 2 * p[i], 0x5eed + (uint64_t)i);
+        np += xs[i].size();
+        ne += (size_t)batch[i];
+    }
+    DevBuf dparams, dout;
+    QQ_HIP(hipMalloc(&dparams.p, np * sizeof(double)));
+    QQ_HIP(hipMalloc(&dout.p, (ne + np) * sizeof(double)));
+    std::vector<const double *> pp(count);
+    std::vector<double *> ep(count), gp(count);
+    {
+        double *dp = static_cast<double *>(dparams.p), *de = static_cast<double *>(dout.p), *dg = de + ne;
+        for (int i = 0; i < count; ++i) {
+            QQ_HIP(hipMemcpy(dp, xs[i].data(), xs[i].size() * sizeof(double), hipMemcpyHostToDevice));
+            pp[i] = dp;
+            ep[i] = de;
+            gp[i] = dg;
+            dp += xs[i].size();
+            de += batch[i];
+            dg += xs[i].size();
+        }
+    }
+    const int eflags = flags | QQ_ENERGY | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE;
+    std::vector<qq_many_options> cands;
+    for (int tpc : {4, 8, 16, 32, 64})
+        for (int mw : {0, 2 * cus}) cands.push_back({tpc, mw, 0.0});
+    size_t need = 0;
+    for (const auto &c : cands) {
+        ManyLayout M;
+        if (qq_status st = plan_many(count, problems, p, batch, eflags, &c, M); st != QQ_OK) return st;
+        need = std::max(need, M.total);
+    }
+    if (qq_status st = check_device_fits(device, need, "the tuning workspace"); st != QQ_OK) return st;
+    DevBuf ws;
+    if (hipMalloc(&ws.p, need) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) for tuning failed", need);
+    double best = INFINITY;
+    qq_many_options bopt{16, 0, 0.0};
+    for (const auto &c : cands) {
+        double ms = 0;
+        auto run = [&]() {
+            return qq_evaluate_many(count, problems, p, batch, pp.data(), eflags, &c, ws.p, need, stream, ep.data(),
+                                    (flags & QQ_GRAD) ? gp.data() : nullptr);
+        };
+        if (qq_status st = time_median(stream, run, ms); st != QQ_OK) return st;
+        if (ms < best) {
+            best = ms;
+            bopt = c;
+        }
+    }
+    char tail[160];
+    std::snprintf(tail, sizeof tail, "\"tiles_per_chunk\":%d,\"max_workgroups\":%d,\"ms\":%.4f}", bopt.tiles_per_chunk,
+                  bopt.max_workgroups, best);
+    if (qq_status st = cache_append(cache_path, key + tail); st != QQ_OK) return st;
+    *out = bopt;
+    if (ms_out) *ms_out = best;
     return QQ_OK;
 }
 

@@ -66,6 +66,11 @@ class QQManyOptions(ctypes.Structure):
                 ("wait_limit_ms", ctypes.c_double)]
 
 
+class QQSchedule(ctypes.Structure):
+    _fields_ = [("workgroups_per_state", ctypes.c_int), ("set_pairing", ctypes.c_int), ("ms", ctypes.c_double),
+                ("pinned", ctypes.c_int), ("from_cache", ctypes.c_int), ("tried", ctypes.c_int)]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -99,6 +104,10 @@ SIGNATURES = {
     "qq_graph_reset": ([_vp, _vp], _int),
     "qq_graph_read": ([_vp, _vp, _vp, _vp, ctypes.POINTER(_int), _int, _vp], _int),
     "qq_graph_destroy": ([_vp], _int),
+    "qq_set_schedule": ([_vp, _int, _int, _int, ctypes.POINTER(QQSchedule)], _int),
+    "qq_get_schedule": ([_vp, _int, _int, _int, ctypes.POINTER(QQSchedule)], _int),
+    "qq_autotune": ([_vp, _int, _int, _int, ctypes.c_char_p, _vp, ctypes.POINTER(QQSchedule)], _int),
+    "qq_autotune_many": ([_int, _vp, _vp, _vp, _int, ctypes.c_char_p, _vp, ctypes.POINTER(QQManyOptions), _dp], _int),
     "qq_profile_enable": ([_int], _int),
     "qq_profile_read": ([ctypes.c_void_p, _int, ctypes.POINTER(_int)], _int),
 }
@@ -365,6 +374,46 @@ def qq_graph_read(graph, batch, p, history=0, stream=None):
 
 def qq_graph_destroy(graph):
     _check(lib().qq_graph_destroy(graph))
+
+
+def _sched_dict(s: QQSchedule):
+    return {"workgroups_per_state": s.workgroups_per_state, "set_pairing": s.set_pairing, "ms": s.ms,
+            "pinned": s.pinned, "from_cache": s.from_cache, "tried": s.tried}
+
+
+def qq_set_schedule(handle, p, batch, flags, schedule):
+    """schedule: dict with workgroups_per_state and set_pairing, or None for the default."""
+    if schedule is None:
+        _check(lib().qq_set_schedule(handle, int(p), int(batch), int(flags), None))
+        return
+    s = QQSchedule(int(schedule["workgroups_per_state"]), int(schedule.get("set_pairing", 0)),
+                   float(schedule.get("ms", 0.0)), 0, 0, 0)
+    _check(lib().qq_set_schedule(handle, int(p), int(batch), int(flags), ctypes.byref(s)))
+
+
+def qq_get_schedule(handle, p, batch, flags):
+    s = QQSchedule()
+    _check(lib().qq_get_schedule(handle, int(p), int(batch), int(flags), ctypes.byref(s)))
+    return _sched_dict(s)
+
+
+def qq_autotune(handle, p, batch, flags, cache_path=None, stream=None):
+    s = QQSchedule()
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().qq_autotune(handle, int(p), int(batch), int(flags), cp, _stream_ptr(stream), ctypes.byref(s)))
+    return _sched_dict(s)
+
+
+def qq_autotune_many(handles, p, batch, flags, cache_path=None, stream=None):
+    """(options dict for qq_evaluate_many, measured ms)."""
+    count, hs, pa, ba = _many_arrays(handles, p, batch)
+    o = QQManyOptions()
+    ms = ctypes.c_double(0.0)
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().qq_autotune_many(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
+                                  int(flags), cp, _stream_ptr(stream), ctypes.byref(o), ctypes.byref(ms)))
+    return {"tiles_per_chunk": o.tiles_per_chunk, "max_workgroups": o.max_workgroups,
+            "wait_limit_ms": o.wait_limit_ms}, ms.value
 
 
 def qq_profile_enable(enable: bool):
