@@ -7,6 +7,10 @@ start through the C ABI (qq_evaluate, QQ_GRAD, device-resident params and
 outputs), in waves of `--wave` starts.  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
+Before timing, the schedule of that evaluation (workgroups per state, pairing of
+the high qubit runs) is autotuned through the C ABI (qq_autotune; HIP-event timed
+candidates, see "schedule" in the output).
+
 Extra measurements in the same run:
   * per-launch HIP-event timing of every pass kernel during the timed steps
     (roofline of the dominant kernel: algorithmic bytes / launch time vs 8 TB/s);
@@ -14,7 +18,10 @@ Extra measurements in the same run:
     set per call) on the same GPU, for the speed-up ratio;
   * a sampled parity check of the timed path against the complex128 fused path;
   * the CPU oracle (single thread, FP64) on a bounded sample of the same
-    instance family, scaled to n = 28.
+    instance family, scaled to n = 28;
+  * the uneven batch (512 dense integer QUBOs, n in 10..22, p in 1..6, energy +
+    gradient): one autotuned persistent launch (qq_evaluate_many) against one
+    qq_evaluate call per problem, both with device-resident inputs and outputs.
 """
 from __future__ import annotations
 
@@ -31,7 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QAOA energy+grad evals/s and HBM GB/s at n=28 p=8, <=1e-5 rel vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2606_26297_amd", "csrc", f)
-               for f in ("qq_device.h", "qq_fast.hip", "qq_kernels.hip")]
+               for f in ("qq_device.h", "qq_passes.h", "qq_fast.hip", "qq_many.hip", "qq_kernels.hip")]
 
 
 def kernel_hash() -> str:
@@ -79,6 +86,83 @@ def cpu_baseline(n_sample=22, starts=2, p=8):
             "seconds": dt}
 
 
+def progress(msg):
+    """Stage lines on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def uneven_batch(dev, reps=5):
+    """The 512-problem uneven batch: persistent launch vs per-problem launches (device-resident)."""
+    import numpy as np
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd import workloads as W
+    from paper_2606_26297_amd.qaoa import Problem
+
+    items = W.workload4()
+    pbs = [Problem(i.H, i.f, i.c0, device=0) for i, _ in items]
+    handles = [pb.handle for pb in pbs]
+    ps = [x.shape[1] // 2 for _, x in items]
+    bs = [x.shape[0] for _, x in items]
+    flags = N.QQ_ENERGY | N.QQ_GRAD | N.QQ_PARAMS_ON_DEVICE | N.QQ_OUT_ON_DEVICE
+    xs = [torch.tensor(x, device=dev) for _, x in items]
+    es = [torch.empty(b, dtype=torch.float64, device=dev) for b in bs]
+    gs = [torch.empty(x.shape, dtype=torch.float64, device=dev) for x in xs]
+    stream = torch.cuda.current_stream(dev)
+    opt, tune_ms = N.qq_autotune_many(handles, ps, bs, flags, None, stream)
+    ws_bytes = N.qq_workspace_size_many(handles, ps, bs, flags, opt)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+
+    def many():
+        N.qq_evaluate_many(handles, ps, bs, xs, flags, opt, ws, ws_bytes, stream, es, gs)
+
+    many()
+    torch.cuda.synchronize()
+    N.qq_profile_enable(True)
+    N.qq_profile_read()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        many()
+    torch.cuda.synchronize()
+    t_many = (time.perf_counter() - t0) / reps
+    N.qq_profile_enable(False)
+    recs = N.qq_profile_read()
+    k_ms = sum(r["ms"] for r in recs) / reps
+    k_bytes = sum(r["bytes"] for r in recs) / reps
+    e_many = [e.clone() for e in es]
+    del ws
+    wsz = max(N.qq_workspace_size(h, p, b, flags) for h, p, b in zip(handles, ps, bs))
+    ws1 = torch.empty(wsz, dtype=torch.uint8, device=dev)
+
+    def per_problem():
+        for h, p, b, x, e, g in zip(handles, ps, bs, xs, es, gs):
+            N.qq_evaluate(h, p, b, x, flags, ws1, wsz, stream, e, g)
+
+    per_problem()
+    torch.cuda.synchronize()
+    N.qq_profile_enable(True)
+    N.qq_profile_read()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        per_problem()
+    torch.cuda.synchronize()
+    t_per = (time.perf_counter() - t0) / reps
+    N.qq_profile_enable(False)
+    launches = len(N.qq_profile_read()) // reps
+    sig = np.array([pb.info.sigma_c for pb in pbs])
+    de = max(float(np.max(np.abs(a.cpu().numpy() - b.cpu().numpy()) / np.maximum(np.abs(b.cpu().numpy()), s)))
+             for a, b, s in zip(e_many, es, sig))
+    return {"workload": "512 dense integer QUBOs, n ~ U{10..22}, p ~ U{1..6}, 1 parameter set each, energy+grad",
+            "persistent_ms": round(1000 * t_many, 3), "persistent_kernel_ms": round(k_ms, 3),
+            "persistent_algorithmic_GBps": round(k_bytes / (k_ms / 1000.0) / 1e9, 1),
+            "per_problem_ms": round(1000 * t_per, 3), "per_problem_launches": launches,
+            "speedup": round(t_per / t_many, 2), "problems_per_s": round(len(items) / t_many, 1),
+            "traffic_bytes_per_launch": load_traffic("many_kernel<%s>" % N.DIAG_TYPE_NAMES[pbs[0].info.diag_bytes]),
+            "options": opt, "autotune_best_ms": round(tune_ms, 3),
+            "energy_rel_vs_per_problem": de}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +175,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="time the built-in default schedule")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch measurement")
+    ap.add_argument("--schedule", default=None, metavar="G:PAIRING",
+                    help="pin this schedule (workgroups per state, set pairing) instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (reference kernel for the traffic counters)")
     args = ap.parse_args()
@@ -109,6 +198,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.uneven_only:
+        progress("uneven batch")
+        print(json.dumps({"uneven_batch": uneven_batch(dev)}), flush=True)
+        return
     inst, x = W.workload3(batch=args.starts, p=args.p, n=args.n)
     pb = Problem(inst.H, inst.f, inst.c0, device=0)
     p, S, B = args.p, args.starts, args.wave
@@ -117,18 +210,29 @@ def main():
     xt = torch.tensor(x, dtype=torch.float64, device=dev)
     e_out = torch.empty(S, dtype=torch.float64, device=dev)
     g_out = torch.empty(S, 2 * p, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    if args.schedule:
+        G, pairing = (int(v) for v in args.schedule.split(":"))
+        N.qq_set_schedule(pb.handle, p, B, flags, {"workgroups_per_state": G, "set_pairing": pairing})
+    schedule = N.qq_get_schedule(pb.handle, p, B, flags)
+    if not args.no_autotune and not args.schedule:
+        progress("autotuning the schedule")
+        schedule = N.qq_autotune(pb.handle, p, B, flags, None, stream)
+        progress(f"schedule {schedule}")
     ws_bytes = pb.workspace_size(p, B, flags)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream(dev)
 
     def step():
         for w in range(S // B):
             N.qq_evaluate(pb.handle, p, B, xt[w * B:(w + 1) * B], flags, ws, ws_bytes, stream,
                           e_out[w * B:(w + 1) * B], g_out[w * B:(w + 1) * B])
 
+    progress(f"warmup x{args.warmup}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    progress(f"timing {args.steps} steps")
     N.qq_profile_enable(True)
     N.qq_profile_read()  # clear
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -172,6 +276,7 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
            "config": {"workload": f"regular3_n{args.n}_p{p}_starts{S}", "n": args.n, "p": p, "starts": S,
                       "wave": B, "state": "complex64", "accumulators": "fp64"},
+           "schedule": schedule,
            "hbm_GBps_step": round(step_bytes / (ms_per_step / 1000.0) / 1e9, 1),
            "algorithmic_bytes_per_eval": step_bytes / S,
            "roofline": roofline, "kernels": kernels}
@@ -197,6 +302,7 @@ def main():
                         "energy_rel": float(np.max(np.abs(e64 - e128) / np.maximum(np.abs(e128), sig))),
                         "grad_rel": float(np.max(np.abs(g64 - g128)) / np.max(np.abs(g128)))}
     if not args.no_plain:
+        progress("plain per-gate comparator")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pb.evaluate_plain(x[0], grad=True)
@@ -206,7 +312,13 @@ def main():
                              "speedup": round(value * tp, 2),
                              "definition": "complex128, one kernel per gate (phase per layer, RX per qubit and "
                                            "layer, energy reduction, unfused adjoint), one parameter set per call"}
+    if not args.no_uneven:
+        del ws
+        torch.cuda.empty_cache()
+        progress("uneven batch")
+        out["uneven_batch"] = uneven_batch(dev)
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
