@@ -347,6 +347,7 @@ typedef struct {
     int batch;      /* states in the launch */
     double bytes;   /* algorithmic bytes moved by the launch */
     double ms;      /* event-timed duration */
+    int part;       /* 1 when the launch applies partitioned (per-QPU local and cross) phases */
 } qq_launch_record;
 
 qq_status qq_profile_enable(int enable);

@@ -480,8 +480,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
     (void)es;
     if (plan.nslots > kMaxSlots) return fail(QQ_E_UNSUPPORTED, "plan needs %d accumulator slots (max %d)", plan.nslots, kMaxSlots);
     // Specialised complex64 kernels serve multi-pass, non-partitioned plans.
-    const bool use_fast =
-        !c128 && plan.sets.size() > 1 && !(flags & QQ_PARTITIONED) && !g_force_generic && pb->n <= kFastMaxN;
+    const bool use_fast = !c128 && plan.sets.size() > 1 && !g_force_generic && pb->n <= kFastMaxN;
     int slot_base = 0;
     for (const auto &pp : plan.passes) {
         if ((int)pp.ops.size() > kMaxOps) return fail(QQ_E_UNSUPPORTED, "pass has %zu ops (max %d)", pp.ops.size(), kMaxOps);
@@ -523,6 +522,10 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
         }
         if (use_fast && pp.fkind >= 0) {
             FastPassParams fp;
+            fp.part = (flags & QQ_PARTITIONED) ? 1 : 0;
+            fp.part_desc = pb->d_part;
+            fp.part_tables = pb->d_tables;
+            fp.cross_diag = pb->d_cross;
             fp.B = B;
             fp.G = L.G;
             fp.p = p;
@@ -552,6 +555,8 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             QQ_HIP(hipEventRecord(rec.stop, stream));
             rec.meta.kind = pp.nstates > 1 ? 2 : 1;
             rec.meta.pass_kind = (use_fast && pp.fkind >= 0) ? pp.fkind : -1;
+            rec.meta.part = (flags & QQ_PARTITIONED) && (pp.fkind == FK_FIRST || pp.fkind == FK_TURN ||
+                                                          pp.fkind == FK_BTURN || !use_fast) ? 1 : 0;
             rec.meta.high = sd.high;
             rec.meta.full = !sd.high || sd.active == 0x0ff0;
             rec.meta.diag_bytes = diag_bytes_of(pb->diag_type);
@@ -1260,7 +1265,10 @@ qq_status qq_set_allocation(qq_problem *pb, int M, const int32_t *qpu_of_var, co
     for (int m = 0; m < M; ++m) {
         pd.table_off[m] = total;
         for (int i = 0; i < n; ++i)
-            if (qpu_of_var[i] == m) pd.vars[m][pd.nvars[m]++] = (uint8_t)i;
+            if (qpu_of_var[i] == m) {
+                pd.vars[m][pd.nvars[m]++] = (uint8_t)i;
+                pd.vmask[m] |= 1ull << i;
+            }
         total += 1ull << pd.nvars[m];
     }
     const int es = diag_bytes_of(pb->diag_type);

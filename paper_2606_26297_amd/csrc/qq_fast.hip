@@ -8,9 +8,9 @@ namespace {
 using namespace dev;
 using namespace passes;
 
-template <int KIND, bool HIGH, bool FULL, typename DT>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KIND >= FK_LASTG ? 3 : 4)))
-fast_pass(const FastArgs a)
+// One workgroup per (state b, workgroup slot g), tiles g, g + G, ...; FP64 partial sums per slot.
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART>
+__device__ __forceinline__ void fast_pass_impl(const FastArgs &a)
 {
     constexpr int NSLOT = kind_slots<KIND>();
     __shared__ float2 lds[kLdsSlots];
@@ -20,7 +20,7 @@ fast_pass(const FastArgs a)
     int b, g;
     block_coords(a.B, a.G, b, g);
     double acc[3] = {0.0, 0.0, 0.0};
-    run_pass<KIND, HIGH, FULL, DT>(a, lds, acc, t, b, g);
+    run_pass<KIND, HIGH, FULL, DT, PART>(a, lds, acc, t, b, g);
 
     if constexpr (NSLOT > 0) {
         const int lane = t & 63, wave = t >> 6;
@@ -38,10 +38,42 @@ fast_pass(const FastArgs a)
     }
 }
 
+template <int KIND, bool HIGH, bool FULL, typename DT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KIND >= FK_LASTG ? 3 : 4)))
+fast_pass(const FastArgs a)
+{
+    fast_pass_impl<KIND, HIGH, FULL, DT, false>(a);
+}
+
+// The same passes with the phase applied as per-QPU local factors and the cross factor
+// (kinds that apply a phase: first, turn, adjoint turn).
+template <int KIND, bool HIGH, bool FULL, typename DT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KIND >= FK_LASTG ? 3 : 4)))
+fast_pass_part(const FastArgs a)
+{
+    fast_pass_impl<KIND, HIGH, FULL, DT, true>(a);
+}
+
+template <int KIND>
+constexpr bool kind_phases()
+{
+    return KIND == FK_FIRST || KIND == FK_TURN || KIND == FK_BTURN;
+}
+
 template <int KIND, bool HIGH, bool FULL>
-hipError_t launch_k(const FastArgs &a, int diag_type, hipStream_t s)
+hipError_t launch_k(const FastArgs &a, int diag_type, bool part, hipStream_t s)
 {
     const dim3 grid((unsigned)(a.B * a.G)), block(kThreads);
+    if constexpr (kind_phases<KIND>()) {
+        if (part) {
+            switch (diag_type) {
+            case DIAG_F64: hipLaunchKernelGGL((fast_pass_part<KIND, HIGH, FULL, double>), grid, block, 0, s, a); break;
+            case DIAG_I32: hipLaunchKernelGGL((fast_pass_part<KIND, HIGH, FULL, int32_t>), grid, block, 0, s, a); break;
+            default: hipLaunchKernelGGL((fast_pass_part<KIND, HIGH, FULL, int16_t>), grid, block, 0, s, a); break;
+            }
+            return hipGetLastError();
+        }
+    }
     switch (diag_type) {
     case DIAG_F64: hipLaunchKernelGGL((fast_pass<KIND, HIGH, FULL, double>), grid, block, 0, s, a); break;
     case DIAG_I32: hipLaunchKernelGGL((fast_pass<KIND, HIGH, FULL, int32_t>), grid, block, 0, s, a); break;
@@ -51,15 +83,15 @@ hipError_t launch_k(const FastArgs &a, int diag_type, hipStream_t s)
 }
 
 template <int KIND>
-hipError_t launch_kind(const FastArgs &a, bool high, int diag_type, hipStream_t s)
+hipError_t launch_kind(const FastArgs &a, bool high, int diag_type, bool part, hipStream_t s)
 {
     if constexpr (KIND == FK_FIRST) {
         if (high) return hipErrorInvalidValue;  // the first pass always mixes qubits 0..11
-        return launch_k<KIND, false, true>(a, diag_type, s);
+        return launch_k<KIND, false, true>(a, diag_type, part, s);
     } else {
-        if (!high) return launch_k<KIND, false, true>(a, diag_type, s);  // the low set is always qubits 0..11
-        return a.active == 0x0ff0 ? launch_k<KIND, true, true>(a, diag_type, s)
-                                  : launch_k<KIND, true, false>(a, diag_type, s);
+        if (!high) return launch_k<KIND, false, true>(a, diag_type, part, s);  // the low set is always qubits 0..11
+        return a.active == 0x0ff0 ? launch_k<KIND, true, true>(a, diag_type, part, s)
+                                  : launch_k<KIND, true, false>(a, diag_type, part, s);
     }
 }
 
@@ -90,15 +122,19 @@ hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassPa
     a.lam = static_cast<float2 *>(pp.lam);
     a.state_stride = pp.state_stride;
     a.partial = pp.partial;
+    a.part = pp.part_desc;
+    a.tables = pp.part_tables;
+    a.cross = pp.cross_diag;
+    const bool part = pp.part != 0;
     switch (kind) {
-    case FK_FIRST: return launch_kind<FK_FIRST>(a, high, diag_type, s);
-    case FK_MID: return launch_kind<FK_MID>(a, high, diag_type, s);
-    case FK_TURN: return launch_kind<FK_TURN>(a, high, diag_type, s);
-    case FK_LAST: return launch_kind<FK_LAST>(a, high, diag_type, s);
-    case FK_LASTG: return launch_kind<FK_LASTG>(a, high, diag_type, s);
-    case FK_BMID: return launch_kind<FK_BMID>(a, high, diag_type, s);
-    case FK_BTURN: return launch_kind<FK_BTURN>(a, high, diag_type, s);
-    case FK_BLAST: return launch_kind<FK_BLAST>(a, high, diag_type, s);
+    case FK_FIRST: return launch_kind<FK_FIRST>(a, high, diag_type, part, s);
+    case FK_MID: return launch_kind<FK_MID>(a, high, diag_type, part, s);
+    case FK_TURN: return launch_kind<FK_TURN>(a, high, diag_type, part, s);
+    case FK_LAST: return launch_kind<FK_LAST>(a, high, diag_type, part, s);
+    case FK_LASTG: return launch_kind<FK_LASTG>(a, high, diag_type, part, s);
+    case FK_BMID: return launch_kind<FK_BMID>(a, high, diag_type, part, s);
+    case FK_BTURN: return launch_kind<FK_BTURN>(a, high, diag_type, part, s);
+    case FK_BLAST: return launch_kind<FK_BLAST>(a, high, diag_type, part, s);
     default: return hipErrorInvalidValue;
     }
 }

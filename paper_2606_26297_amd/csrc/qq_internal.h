@@ -70,6 +70,7 @@ struct PartDesc {
     int nvars[QQ_MAX_QPUS];
     uint64_t table_off[QQ_MAX_QPUS];  // element offset of table m inside the packed tables buffer
     uint8_t vars[QQ_MAX_QPUS][QQ_MAX_N];
+    uint64_t vmask[QQ_MAX_QPUS];      // bit i set when variable i + 1 sits on QPU m
 };
 
 struct PassArgs {
@@ -132,6 +133,10 @@ hipError_t launch_local_tables(int n, int diag_type, const PartDesc *d_pd, const
 // Specialised complex64 pass kernels (qq_fast.hip): one kernel per pass kind.
 enum FastPassKind : int { FK_FIRST = 0, FK_MID, FK_TURN, FK_LAST, FK_LASTG, FK_BMID, FK_BTURN, FK_BLAST, FK_SINGLE };
 struct FastPassParams {
+    int part;  // 1: the phase is the product of the per-QPU local factors and the cross factor
+    const PartDesc *part_desc;  // device
+    const void *part_tables;
+    const void *cross_diag;
     int B, G, p, k;
     uint64_t tiles, dim_mask;
     int pos4, pos8, w1, w2, active, store_psi;

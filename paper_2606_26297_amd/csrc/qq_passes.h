@@ -351,7 +351,118 @@ struct FastArgs {
     float2 *lam;
     uint64_t state_stride;
     double *partial;
+    const PartDesc *part;  // partitioned phases (PART bodies only)
+    const void *tables;    // packed per-QPU local tables
+    const void *cross;     // cross-QPU diagonal, 2^n entries
 };
+
+// ---- partitioned phase (eq. (16)) --------------------------------------------------------------
+// The cost splits into per-QPU local parts C_m, each a function of that QPU's variables only (table
+// m is indexed by those bits in ascending variable order), and the cross part C_x (a diagonal over
+// all of z).  The phase is applied as the product of exp(-i gamma C_m), m = 0..M-1, and
+// exp(-i gamma C_x), each argument reduced on its own.  Table index of amplitude z for QPU m: the
+// bits of z on the QPU's variables, gathered in order.  The gather is additive over disjoint bit
+// sets, so for z = zb | e | (register bits) it is gather(zb) (per tile, scalar) + gather(e) (per
+// lane) + the register bits' contributions (scalar, one per register bit).
+
+// 2^(rank of qubit q among the QPU's variables) if q is on the QPU, else 0.
+__device__ __forceinline__ uint32_t part_contrib(uint64_t vmask, int q)
+{
+    return ((vmask >> q) & 1ull) ? (1u << __popcll(vmask & ((1ull << q) - 1ull))) : 0u;
+}
+
+// Gather of the bits of zb on the QPU's variables (wave-uniform), without a loop over the
+// variables (a data-dependent loop here would split the tile body and raise its register demand):
+// the compress method of Hacker's Delight (sec. 7-4), six fixed steps that move each selected bit
+// right by the number of unselected mask positions below it, one bit of that count per step.
+__device__ __forceinline__ uint32_t part_gather(uint64_t zb, uint64_t vmask)
+{
+    uint64_t x = zb & vmask, m = vmask;
+    uint64_t mk = ~m << 1;  // positions whose count of zeros below them is still to be moved
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        uint64_t mp = mk ^ (mk << 1);  // prefix parity of mk: odd count of mk bits at or below
+        mp ^= mp << 2;
+        mp ^= mp << 4;
+        mp ^= mp << 8;
+        mp ^= mp << 16;
+        mp ^= mp << 32;
+        const uint64_t mv = mp & m;  // mask bits that move by 2^i in this step
+        m = (m ^ mv) | (mv >> (1 << i));
+        const uint64_t t = x & mv;
+        x = (x ^ t) | (t >> (1 << i));
+        mk &= ~mp;
+    }
+    return (uint32_t)x;
+}
+
+// The phase of the partitioned cost for this thread's 16 registers, as angles in revolutions:
+// uf[r] = the sum over the local factors and the cross factor of (gamma / 2 pi) C_m(z), each
+// term reduced on its own in FP64 to [-1/2, 1/2], the sum reduced again and rounded to float.
+// Layout: lanes hold qubits 0..3 (lane_lo) and qh, qh + 1 (lane_hi); registers hold qubits
+// qr..qr+3 (register stride rs); zb is the tile's wave-uniform first index; vd the lane's byte
+// offset into a DT diagonal.  The angles do not depend on the state, so a pass can form them
+// before it loads any amplitude.
+template <typename DT>
+__device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &a, double g2pi, uint64_t zb,
+                                            uint32_t lane_lo, uint32_t lane_hi, int qh, int qr, uint64_t rs,
+                                            uint32_t vd)
+{
+    // registers in two halves of 8, so the FP64 sums take 16 VGPRs, not 32
+    constexpr int H = kRegs / 2;
+    // opaque here, so the masks and lane tests derived from them are formed per tile instead of
+    // hoisted out of the tile loop (where they would hold dozens of scalar registers throughout)
+    asm volatile("" : "+s"(qh), "+s"(qr), "+v"(lane_lo), "+v"(lane_hi));
+    const uint64_t cross_a = (uint64_t)a.cross;
+    const int M = a.part->nparts;
+    const DT *tables = static_cast<const DT *>(a.tables);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        double u[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const int r = h * H + i;
+            const double w = g2pi * (double)gld<DT>(cross_a + (zb + r * rs) * sizeof(DT), vd);
+            u[i] = w - rint(w);
+            QQ_CHUNK_FENCE(i);
+        }
+        for (int m = 0; m < M; ++m) {
+            const uint64_t vm = a.part->vmask[m];
+            const uint64_t tab = (uint64_t)(tables + a.part->table_off[m]);
+            uint32_t L = part_gather(zb, vm);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) L += ((lane_lo >> j) & 1u) ? part_contrib(vm, j) : 0u;
+            L += (lane_hi & 1u) ? part_contrib(vm, qh) : 0u;
+            L += (lane_hi & 2u) ? part_contrib(vm, qh + 1) : 0u;
+            const uint32_t c0 = part_contrib(vm, qr), c1 = part_contrib(vm, qr + 1), c2 = part_contrib(vm, qr + 2),
+                           c3 = part_contrib(vm, qr + 3);
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const int r = h * H + i;
+                const uint32_t idx =
+                    L + ((r & 1) ? c0 : 0u) + ((r & 2) ? c1 : 0u) + ((r & 4) ? c2 : 0u) + ((r & 8) ? c3 : 0u);
+                const double w = g2pi * (double)gld<DT>(tab, idx * (uint32_t)sizeof(DT));
+                u[i] += w - rint(w);
+                QQ_CHUNK_FENCE(i);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < H; ++i) uf[h * H + i] = (float)(u[i] - rint(u[i]));
+    }
+}
+
+// Multiply the states ST (bit 0 psi, bit 1 lambda) by exp(-+ 2 pi i uf[r]) (INV: the inverse).
+template <int NS, int ST, bool INV>
+__device__ __forceinline__ void apply_angles(float2 (&v)[NS][kRegs], const float (&uf)[kRegs])
+{
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+        const float c = __builtin_amdgcn_cosf(uf[r]);
+        const float s = INV ? -__builtin_amdgcn_sinf(uf[r]) : __builtin_amdgcn_sinf(uf[r]);
+        if constexpr (ST & 1) rot_phase<float>(v[0][r], c, s);
+        if constexpr (NS > 1 && (ST & 2)) rot_phase<float>(v[NS - 1][r], c, s);
+    }
+}
 
 template <int KIND>
 constexpr int kind_states()
@@ -366,7 +477,7 @@ constexpr int kind_slots()
 }
 
 // The tile loop of one pass kind.  FB1 / FB2: form of the first / second mixer coefficient.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool FB1, bool FB2>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool FB1, bool FB2>
 __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g,
                                           const MixCoef &c1, const MixCoef &c2, double g2pi)
 {
@@ -404,12 +515,20 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         auto st1f = [&](uint64_t arr, int r, float2 x, uint64_t rs) { gst(arr + (b1 + r * rs) * 8, vs1, x); };
 
         if constexpr (KIND == FK_FIRST) {
+            if constexpr (PART) {
+                float uf[kRegs];
+                part_angles<DT>(uf, a, g2pi, b2, lane_lo, lane_hi, a.pos4, a.pos8, rs2, vd2);
 #pragma unroll
-            for (int r = 0; r < kRegs; ++r) {
-                float c, s;
-                phase_rev(g2pi, cz2(r), c, s);
-                v[0][r] = make_float2((float)a.amp0 * c, -(float)a.amp0 * s);
-                QQ_CHUNK_FENCE(r);
+                for (int r = 0; r < kRegs; ++r) v[0][r] = make_float2((float)a.amp0, 0.0f);
+                apply_angles<NS, 1, false>(v, uf);
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) {
+                    float c, s;
+                    phase_rev(g2pi, cz2(r), c, s);
+                    v[0][r] = make_float2((float)a.amp0 * c, -(float)a.amp0 * s);
+                    QQ_CHUNK_FENCE(r);
+                }
             }
             double unused = 0.0;
             mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
@@ -426,12 +545,18 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
             } else if constexpr (KIND == FK_TURN) {
+                if constexpr (PART) {
+                    float uf[kRegs];
+                    part_angles<DT>(uf, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, rs1, vd1);
+                    apply_angles<NS, 1, false>(v, uf);
+                } else {
 #pragma unroll
-                for (int r = 0; r < kRegs; ++r) {
-                    float c, s;
-                    phase_rev(g2pi, cz1(r), c, s);
-                    rot_phase<float>(v[0][r], c, s);
-                    QQ_CHUNK_FENCE(r);
+                    for (int r = 0; r < kRegs; ++r) {
+                        float c, s;
+                        phase_rev(g2pi, cz1(r), c, s);
+                        rot_phase<float>(v[0][r], c, s);
+                        QQ_CHUNK_FENCE(r);
+                    }
                 }
                 mix_op<HIGH, FULL, 1, 1, 1, false, FB2>(lds, v, t, a.active, c2, unused);
                 const uint64_t rss = opaque_u64(rs2);
@@ -474,6 +599,10 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) st2f(lam_a, r, v[1][r], rss);
         } else {
+            // partitioned adjoint turn: the un-phase angles (layout 1) before any amplitude is live
+            float uf_b[kRegs];
+            if constexpr (KIND == FK_BTURN && PART)
+                part_angles<DT>(uf_b, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, rs1, vd1);
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) {
                 v[0][r] = ld2(psi_a, r);
@@ -497,7 +626,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     const float2 ps = v[0][r], la = v[1][r];
                     const float im = fmaf(la.x, ps.y, -la.y * ps.x);
                     gg = fma(cz, (double)im, gg);
-                    if constexpr (KIND == FK_BTURN) {
+                    if constexpr (KIND == FK_BTURN && !PART) {
                         float c, s;
                         phase_rev(g2pi, cz, c, s);
                         rot_phase<float>(v[0][r], c, -s);
@@ -506,6 +635,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     QQ_CHUNK_FENCE(r);
                 }
                 acc[1] += gg;
+                if constexpr (KIND == FK_BTURN && PART) apply_angles<NS, 3, true>(v, uf_b);
                 if constexpr (KIND == FK_BTURN) {
                     double gb2 = 0.0;
                     mix_op<HIGH, FULL, 1, 2, 3, true, FB2>(lds, v, t, a.active, c2, gb2);
@@ -525,7 +655,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
 // Layer constants of one pass for parameter set x, then one uniform dispatch on
 // the forms of the (up to two) mixer coefficients, so the butterfly code of each
 // path has no form branch.  Tiles g, g + a.G, ... below a.tiles.
-template <int KIND, bool HIGH, bool FULL, typename DT>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART = false>
 __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g)
 {
     const double *x = a.params + (size_t)b * 2 * a.p;
@@ -554,15 +684,15 @@ __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double 
     constexpr bool TWO = KIND == FK_TURN || KIND == FK_LASTG || KIND == FK_BTURN;
     if constexpr (!FULL) {
         // general butterflies: one body serves both forms
-        pass_body<KIND, HIGH, FULL, DT, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        pass_body<KIND, HIGH, FULL, DT, PART, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
         return;
     }
     const int sel = (c1.formB ? 1 : 0) | (TWO && c2.formB ? 2 : 0);
-    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
-    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, true, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, PART, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, PART, true, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
     else if constexpr (TWO) {
-        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, false, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
-        else pass_body<KIND, HIGH, FULL, DT, true, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, PART, false, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        else pass_body<KIND, HIGH, FULL, DT, PART, true, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
     }
 }
 

@@ -50,7 +50,7 @@ class QQError(RuntimeError):
 class QQLaunchRecord(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("pass_kind", ctypes.c_int), ("high", ctypes.c_int),
                 ("full", ctypes.c_int), ("diag_bytes", ctypes.c_int), ("c128", ctypes.c_int), ("n", ctypes.c_int), ("batch", ctypes.c_int),
-                ("bytes", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("ms", ctypes.c_double), ("part", ctypes.c_int)]
 
 
 class QQInfo(ctypes.Structure):
@@ -426,7 +426,8 @@ def qq_profile_read(max_records: int = 1 << 16):
     cnt = _int(0)
     _check(lib().qq_profile_read(ctypes.cast(buf, ctypes.c_void_p), max_records, ctypes.byref(cnt)))
     return [{"kind": r.kind, "pass_kind": r.pass_kind, "high": r.high, "full": r.full, "diag_bytes": r.diag_bytes,
-             "c128": r.c128, "n": r.n, "batch": r.batch, "bytes": r.bytes, "ms": r.ms} for r in buf[:cnt.value]]
+             "c128": r.c128, "n": r.n, "batch": r.batch, "bytes": r.bytes, "ms": r.ms, "part": r.part}
+            for r in buf[:cnt.value]]
 
 
 PASS_KIND_NAMES = ["FK_FIRST", "FK_MID", "FK_TURN", "FK_LAST", "FK_LASTG", "FK_BMID", "FK_BTURN", "FK_BLAST"]
@@ -442,6 +443,7 @@ def kernel_name(rec) -> str:
     dt = DIAG_TYPE_NAMES[rec["diag_bytes"]]
     if rec["pass_kind"] >= 0:
         tf = lambda x: "true" if x else "false"  # noqa: E731
-        return f"fast_pass<{rec['pass_kind']}, {tf(rec['high'])}, {tf(rec['full'])}, {dt}>"
+        name = "fast_pass_part" if rec.get("part") else "fast_pass"
+        return f"{name}<{rec['pass_kind']}, {tf(rec['high'])}, {tf(rec['full'])}, {dt}>"
     real = "double" if rec["c128"] else "float"
     return f"pass_kernel<{real}, {2 if rec['kind'] == 2 else 1}, {dt}>"
