@@ -44,9 +44,12 @@ qq_status fail(qq_status st, const char *fmt, ...)
     } while (0)
 
 constexpr double kTwo31 = 2147483648.0;
-// The specialised kernels address a lane's amplitudes with a 32-bit byte offset
-// of at most (15 + 3 * 2^pos8) * 8 bytes, which fits while pos8 <= 27, i.e. n <= 31.
-constexpr int kFastMaxN = 31;
+// The specialised kernels serve every n up to QQ_MAX_N: a lane's amplitudes are addressed with a
+// 32-bit byte offset of at most (15 + 3 * 2^pos8) * 8 bytes while pos8 <= 27, and with a 64-bit one
+// for the partial high set of n >= 32 (pos8 >= 28).  The persistent many-problem kernel keeps the
+// 32-bit form only, so it serves n <= 31.
+constexpr int kFastMaxN = QQ_MAX_N;
+constexpr int kManyMaxN = 31;
 constexpr double kTwo15 = 32768.0;
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -1004,8 +1007,8 @@ qq_status validate_many(int count, qq_problem *const *pbs, const int *p, const i
         if (pbs[i]->device != pbs[0]->device)
             return fail(QQ_E_INVALID, "problems[%d] is on device %d, problems[0] on %d", i, pbs[i]->device,
                         pbs[0]->device);
-        if (pbs[i]->n > kFastMaxN)
-            return fail(QQ_E_UNSUPPORTED, "problems[%d]: n = %d above %d (use qq_evaluate)", i, pbs[i]->n, kFastMaxN);
+        if (pbs[i]->n > kManyMaxN)
+            return fail(QQ_E_UNSUPPORTED, "problems[%d]: n = %d above %d (use qq_evaluate)", i, pbs[i]->n, kManyMaxN);
         if (p[i] < 1 || p[i] > QQ_MAX_P) return fail(QQ_E_INVALID, "p[%d] = %d outside [1, %d]", i, p[i], QQ_MAX_P);
         if (batch[i] < 1) return fail(QQ_E_INVALID, "batch[%d] = %d must be >= 1", i, batch[i]);
     }

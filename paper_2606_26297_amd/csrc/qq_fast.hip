@@ -9,7 +9,7 @@ using namespace dev;
 using namespace passes;
 
 // One workgroup per (state b, workgroup slot g), tiles g, g + G, ...; FP64 partial sums per slot.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool PART>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool WIDE = false>
 __device__ __forceinline__ void fast_pass_impl(const FastArgs &a)
 {
     constexpr int NSLOT = kind_slots<KIND>();
@@ -20,7 +20,7 @@ __device__ __forceinline__ void fast_pass_impl(const FastArgs &a)
     int b, g;
     block_coords(a.B, a.G, b, g);
     double acc[3] = {0.0, 0.0, 0.0};
-    run_pass<KIND, HIGH, FULL, DT, PART>(a, lds, acc, t, b, g);
+    run_pass<KIND, HIGH, FULL, DT, PART, WIDE>(a, lds, acc, t, b, g);
 
     if constexpr (NSLOT > 0) {
         const int lane = t & 63, wave = t >> 6;
@@ -54,6 +54,22 @@ fast_pass_part(const FastArgs a)
     fast_pass_impl<KIND, HIGH, FULL, DT, true>(a);
 }
 
+// Partial high sets whose upper run starts at qubit 28 or above (n >= 32): a lane's offset in
+// the layout whose lane bits sit on that run can exceed 4 GiB, so it is kept in 64 bits.
+template <int KIND, typename DT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KIND >= FK_LASTG ? 3 : 4)))
+fast_pass_wide(const FastArgs a)
+{
+    fast_pass_impl<KIND, true, false, DT, false, true>(a);
+}
+
+template <int KIND, typename DT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KIND >= FK_LASTG ? 3 : 4)))
+fast_pass_part_wide(const FastArgs a)
+{
+    fast_pass_impl<KIND, true, false, DT, true, true>(a);
+}
+
 template <int KIND>
 constexpr bool kind_phases()
 {
@@ -83,6 +99,28 @@ hipError_t launch_k(const FastArgs &a, int diag_type, bool part, hipStream_t s)
 }
 
 template <int KIND>
+hipError_t launch_wide(const FastArgs &a, int diag_type, bool part, hipStream_t s)
+{
+    const dim3 grid((unsigned)(a.B * a.G)), block(kThreads);
+    if constexpr (kind_phases<KIND>()) {
+        if (part) {
+            switch (diag_type) {
+            case DIAG_F64: hipLaunchKernelGGL((fast_pass_part_wide<KIND, double>), grid, block, 0, s, a); break;
+            case DIAG_I32: hipLaunchKernelGGL((fast_pass_part_wide<KIND, int32_t>), grid, block, 0, s, a); break;
+            default: hipLaunchKernelGGL((fast_pass_part_wide<KIND, int16_t>), grid, block, 0, s, a); break;
+            }
+            return hipGetLastError();
+        }
+    }
+    switch (diag_type) {
+    case DIAG_F64: hipLaunchKernelGGL((fast_pass_wide<KIND, double>), grid, block, 0, s, a); break;
+    case DIAG_I32: hipLaunchKernelGGL((fast_pass_wide<KIND, int32_t>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((fast_pass_wide<KIND, int16_t>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int KIND>
 hipError_t launch_kind(const FastArgs &a, bool high, int diag_type, bool part, hipStream_t s)
 {
     if constexpr (KIND == FK_FIRST) {
@@ -90,8 +128,13 @@ hipError_t launch_kind(const FastArgs &a, bool high, int diag_type, bool part, h
         return launch_k<KIND, false, true>(a, diag_type, part, s);
     } else {
         if (!high) return launch_k<KIND, false, true>(a, diag_type, part, s);  // the low set is always qubits 0..11
-        return a.active == 0x0ff0 ? launch_k<KIND, true, true>(a, diag_type, part, s)
-                                  : launch_k<KIND, true, false>(a, diag_type, part, s);
+        // largest layout-1 lane offset: (15 + 3 * 2^pos8) amplitudes of 8 bytes
+        const bool wide = ((15ull + (3ull << a.pos8)) * 8ull) >> 32 != 0;
+        if (a.active == 0x0ff0) {
+            if (wide) return hipErrorInvalidValue;  // full high sets stay below qubit 28 for n <= 34
+            return launch_k<KIND, true, true>(a, diag_type, part, s);
+        }
+        return wide ? launch_wide<KIND>(a, diag_type, part, s) : launch_k<KIND, true, false>(a, diag_type, part, s);
     }
 }
 

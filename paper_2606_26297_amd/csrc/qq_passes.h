@@ -48,8 +48,10 @@ __device__ __forceinline__ void phase_rev(double g2pi, double cz, float &c, floa
     if (((r) & 3) == 3) __builtin_amdgcn_sched_barrier(0)
 
 // Global-memory access through a wave-uniform 64-bit base and a 32-bit per-thread offset.
-template <typename T>
-__device__ __forceinline__ T gld(uint64_t sbase, uint32_t voff)
+// voff: a 32-bit per-lane byte offset (scalar base + vector offset addressing), or 64-bit where
+// a lane's offset can reach 4 GiB (the strided layout of the highest qubit runs at n >= 32).
+template <typename T, typename O = uint32_t>
+__device__ __forceinline__ T gld(uint64_t sbase, O voff)
 {
     if constexpr (std::is_same<T, float2>::value) {
         // state amplitudes are streamed once per pass: non-temporal
@@ -60,7 +62,8 @@ __device__ __forceinline__ T gld(uint64_t sbase, uint32_t voff)
         return *reinterpret_cast<const T __attribute__((address_space(1))) *>(sbase + voff);
     }
 }
-__device__ __forceinline__ void gst(uint64_t sbase, uint32_t voff, float2 x)
+template <typename O = uint32_t>
+__device__ __forceinline__ void gst(uint64_t sbase, O voff, float2 x)
 {
     const uint64_t u = (uint64_t)__float_as_uint(x.x) | ((uint64_t)__float_as_uint(x.y) << 32);
     __builtin_nontemporal_store(u, reinterpret_cast<uint64_t __attribute__((address_space(1))) *>(sbase + voff));
@@ -403,10 +406,9 @@ __device__ __forceinline__ uint32_t part_gather(uint64_t zb, uint64_t vmask)
 // qr..qr+3 (register stride rs); zb is the tile's wave-uniform first index; vd the lane's byte
 // offset into a DT diagonal.  The angles do not depend on the state, so a pass can form them
 // before it loads any amplitude.
-template <typename DT>
+template <typename DT, typename O>
 __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &a, double g2pi, uint64_t zb,
-                                            uint32_t lane_lo, uint32_t lane_hi, int qh, int qr, uint64_t rs,
-                                            uint32_t vd)
+                                            uint32_t lane_lo, uint32_t lane_hi, int qh, int qr, uint64_t rs, O vd)
 {
     // registers in two halves of 8, so the FP64 sums take 16 VGPRs, not 32
     constexpr int H = kRegs / 2;
@@ -477,7 +479,7 @@ constexpr int kind_slots()
 }
 
 // The tile loop of one pass kind.  FB1 / FB2: form of the first / second mixer coefficient.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool FB1, bool FB2>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool WIDE, bool FB1, bool FB2>
 __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g,
                                           const MixCoef &c1, const MixCoef &c2, double g2pi)
 {
@@ -489,9 +491,12 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
     //   layout 1: lanes -> qubits 0..3, pos8, pos8+1; waves -> pos8+2, pos8+3; registers -> pos4..pos4+3
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(t >> 6);
     const uint32_t lane_lo = t & 15, lane_hi = (t >> 4) & 3;
-    const uint32_t e2 = lane_lo + (lane_hi << a.pos4), e1 = lane_lo + (lane_hi << a.pos8);
-    const uint32_t vs2 = e2 * (uint32_t)sizeof(float2), vs1 = e1 * (uint32_t)sizeof(float2);
-    const uint32_t vd2 = e2 * (uint32_t)sizeof(DT), vd1 = e1 * (uint32_t)sizeof(DT);
+    // WIDE: the layout-1 lane offsets (lane bits on qubits pos8, pos8 + 1) need 64 bits
+    using O1 = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+    const uint32_t e2 = lane_lo + (lane_hi << a.pos4);
+    const O1 e1 = (O1)lane_lo + ((O1)lane_hi << a.pos8);
+    const uint32_t vs2 = e2 * (uint32_t)sizeof(float2), vd2 = e2 * (uint32_t)sizeof(DT);
+    const O1 vs1 = e1 * (O1)sizeof(float2), vd1 = e1 * (O1)sizeof(DT);
     const uint64_t w2 = (uint64_t)wave << (a.pos4 + 2), w1 = (uint64_t)wave << (a.pos8 + 2);
     const uint64_t psi_a = (uint64_t)(a.psi + (size_t)b * a.state_stride);
     const uint64_t lam_a = (uint64_t)(a.lam + (size_t)b * a.state_stride);
@@ -655,7 +660,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
 // Layer constants of one pass for parameter set x, then one uniform dispatch on
 // the forms of the (up to two) mixer coefficients, so the butterfly code of each
 // path has no form branch.  Tiles g, g + a.G, ... below a.tiles.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool PART = false>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART = false, bool WIDE = false>
 __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g)
 {
     const double *x = a.params + (size_t)b * 2 * a.p;
@@ -684,15 +689,15 @@ __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double 
     constexpr bool TWO = KIND == FK_TURN || KIND == FK_LASTG || KIND == FK_BTURN;
     if constexpr (!FULL) {
         // general butterflies: one body serves both forms
-        pass_body<KIND, HIGH, FULL, DT, PART, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
         return;
     }
     const int sel = (c1.formB ? 1 : 0) | (TWO && c2.formB ? 2 : 0);
-    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, PART, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
-    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, PART, true, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
     else if constexpr (TWO) {
-        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, PART, false, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
-        else pass_body<KIND, HIGH, FULL, DT, PART, true, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        else pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
     }
 }
 

@@ -444,6 +444,8 @@ def kernel_name(rec) -> str:
     if rec["pass_kind"] >= 0:
         tf = lambda x: "true" if x else "false"  # noqa: E731
         name = "fast_pass_part" if rec.get("part") else "fast_pass"
+        if rec["high"] and not rec["full"] and rec["n"] >= 32:  # 64-bit lane offsets
+            return f"{name}_wide<{rec['pass_kind']}, {dt}>"
         return f"{name}<{rec['pass_kind']}, {tf(rec['high'])}, {tf(rec['full'])}, {dt}>"
     real = "double" if rec["c128"] else "float"
     return f"pass_kernel<{real}, {2 if rec['kind'] == 2 else 1}, {dt}>"
