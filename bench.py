@@ -21,7 +21,10 @@ Extra measurements in the same run:
     instance family, scaled to n = 28;
   * the uneven batch (512 dense integer QUBOs, n in 10..22, p in 1..6, energy +
     gradient): one autotuned persistent launch (qq_evaluate_many) against one
-    qq_evaluate call per problem, both with device-resident inputs and outputs.
+    qq_evaluate call per problem, both with device-resident inputs and outputs;
+  * the multi-QPU workload at full size (n = 32, 4 QPUs of 8, p = 2, 2 parameter
+    sets): monolithic against partitioned (per-QPU local and cross phases)
+    energy + gradient, with the cross-coupling count and remote-CNOT estimate.
 """
 from __future__ import annotations
 
@@ -163,6 +166,51 @@ def uneven_batch(dev, reps=5):
             "energy_rel_vs_per_problem": de}
 
 
+def multi_qpu(dev):
+    """The n = 32 multi-QPU workload: monolithic vs partitioned energy + gradient (device-resident)."""
+    import numpy as np
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd import workloads as W
+    from paper_2606_26297_amd.qaoa import Problem
+
+    inst, x, alloc = W.workload5()
+    n, p, B = inst.H.shape[0], x.shape[1] // 2, x.shape[0]
+    pb = Problem(inst.H, inst.f, inst.c0, device=0)
+    caps = [int(c) for c in np.bincount(alloc)]
+    cross, remote = pb.set_allocation(alloc, len(caps), caps)
+    xt = torch.tensor(x, device=dev)
+    out = {"workload": f"dense N(0,1) upper-triangular QUBO, n = {n}, p = {p}, {B} parameter sets, "
+                       f"{len(caps)} QPUs x {caps[0]} (contiguous), complex64 energy+grad",
+           "cross_terms": cross, "remote_cx_per_layer": remote, "remote_cx_circuit": remote * p}
+    res = {}
+    for name, part in (("monolithic", False), ("partitioned", True)):
+        pb.evaluate(xt, grad=True, partitioned=part)
+        torch.cuda.synchronize()
+        N.qq_profile_enable(True)
+        N.qq_profile_read()
+        t0 = time.perf_counter()
+        e, g = pb.evaluate(xt, grad=True, partitioned=part)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        N.qq_profile_enable(False)
+        recs = N.qq_profile_read()
+        by = sum(r["bytes"] for r in recs)
+        ms = sum(r["ms"] for r in recs)
+        res[name] = (e.cpu().numpy(), g.cpu().numpy())
+        out[name] = {"ms": round(1000 * dt, 2), "algorithmic_GBps": round(by / (ms / 1000.0) / 1e9, 1),
+                     "launches": len(recs)}
+    sig = pb.info.sigma_c
+    (e0, g0), (e1, g1) = res["monolithic"], res["partitioned"]
+    out["partitioned_overhead"] = round(out["partitioned"]["ms"] / out["monolithic"]["ms"], 3)
+    out["partitioned_vs_monolithic"] = {
+        "energy_rel": float(np.max(np.abs(e1 - e0) / np.maximum(np.abs(e0), sig))),
+        "grad_rel": float(np.max(np.abs(g1 - g0)) / np.max(np.abs(g0)))}
+    pb.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +226,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="time the built-in default schedule")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch measurement")
+    ap.add_argument("--no-multi-qpu", action="store_true", help="skip the n = 32 multi-QPU measurement")
     ap.add_argument("--schedule", default=None, metavar="G:PAIRING",
                     help="pin this schedule (workgroups per state, set pairing) instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -312,11 +361,17 @@ def main():
                              "speedup": round(value * tp, 2),
                              "definition": "complex128, one kernel per gate (phase per layer, RX per qubit and "
                                            "layer, energy reduction, unfused adjoint), one parameter set per call"}
+    del ws
+    pb.close()
+    torch.cuda.empty_cache()
     if not args.no_uneven:
-        del ws
-        torch.cuda.empty_cache()
         progress("uneven batch")
         out["uneven_batch"] = uneven_batch(dev)
+        torch.cuda.empty_cache()
+    if not args.no_multi_qpu:
+        progress("multi-QPU n = 32")
+        out["multi_qpu"] = multi_qpu(dev)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()
