@@ -22,6 +22,8 @@ Extra measurements in the same run:
   * the uneven batch (512 dense integer QUBOs, n in 10..22, p in 1..6, energy +
     gradient): one autotuned persistent launch (qq_evaluate_many) against one
     qq_evaluate call per problem, both with device-resident inputs and outputs;
+  * the cost diagonal, min/max, probabilities and top-k kernels on the timed
+    instance (one parameter set);
   * the multi-QPU workload at full size (n = 32, 4 QPUs of 8, p = 2, 2 parameter
     sets): monolithic against partitioned (per-QPU local and cross phases)
     energy + gradient, with the cross-coupling count and remote-CNOT estimate.
@@ -164,6 +166,40 @@ def uneven_batch(dev, reps=5):
             "traffic_bytes_per_launch": load_traffic("many_kernel<%s>" % N.DIAG_TYPE_NAMES[pbs[0].info.diag_bytes]),
             "options": opt, "autotune_best_ms": round(tune_ms, 3),
             "energy_rel_vs_per_problem": de}
+
+
+def aux_kernels(dev, inst, x):
+    """Cost diagonal, min/max, probabilities and top-k on the timed instance (one parameter set)."""
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd.qaoa import Problem
+
+    N.qq_profile_enable(True)
+    N.qq_profile_read()
+    pb = Problem(inst.H, inst.f, inst.c0, device=0)
+    torch.cuda.synchronize()
+    p = x.shape[1] // 2
+    flags = N.QQ_PARAMS_ON_DEVICE | N.QQ_OUT_ON_DEVICE
+    xt = torch.tensor(x[0], device=dev)
+    prob = torch.empty(1 << pb.n, dtype=torch.float64, device=dev)
+    N.qq_probabilities(pb.handle, p, xt, flags, prob)
+    idx, pr, cost = N.qq_topk(pb.handle, p, xt, N.QQ_PARAMS_ON_DEVICE, 10)
+    torch.cuda.synchronize()
+    N.qq_profile_enable(False)
+    recs = N.qq_profile_read()
+    out = {}
+    for r in recs:
+        if r["kind"] < 5:
+            continue
+        k = N.kernel_name(r)
+        out[k] = {"ms": round(r["ms"], 4), "algorithmic_GBps": round(r["bytes"] / (r["ms"] / 1000.0) / 1e9, 1),
+                  "bytes": r["bytes"]}
+    out["top1"] = {"index": int(idx[0]), "probability": float(pr[0]), "cost": float(cost[0]),
+                   "probability_sum": float(prob.sum())}
+    del prob
+    pb.close()
+    return out
 
 
 def multi_qpu(dev):
@@ -363,6 +399,9 @@ def main():
                                            "layer, energy reduction, unfused adjoint), one parameter set per call"}
     del ws
     pb.close()
+    torch.cuda.empty_cache()
+    progress("cost diagonal, probabilities, top-k")
+    out["aux"] = aux_kernels(dev, inst, x)
     torch.cuda.empty_cache()
     if not args.no_uneven:
         progress("uneven batch")

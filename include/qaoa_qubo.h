@@ -290,7 +290,8 @@ qq_status qq_autotune_many(int count, qq_problem *const *problems, const int *p,
  * The handle owns the evaluation workspace, the Adam moments, the step counter
  * and the last step's energies and gradients (all device memory, allocated here
  * once).  The step counter and moments start at zero.  The problem handle and
- * params must outlive the graph.
+ * params must outlive the graph: qq_problem_destroy and qq_set_allocation on
+ * the problem return QQ_E_INVALID while a graph captured on it exists.
  * qq_graph_run       replays the captured step `steps` times on `stream`
  *                    (asynchronous; no allocation, no host work per step).
  * qq_graph_step_eager launches the same kernels directly (one step).
@@ -336,7 +337,8 @@ qq_status qq_evaluate_plain(qq_problem *prob, int p, const double *params, int f
  */
 typedef struct {
     int kind;       /* 1: forward pass (one state), 2: adjoint pass (psi and lambda), 3: final reduction,
-                       4: persistent many-problem launch */
+                       4: persistent many-problem launch, 5: cost diagonal, 6: min/max of C,
+                       7: probabilities, 8: top-k */
     int pass_kind;  /* complex64 specialised kernel: 0 first, 1 mid, 2 turn, 3 last, 4 last+adjoint seed,
                        5 adjoint mid, 6 adjoint turn, 7 adjoint last; -1: generic pass kernel */
     int high;       /* 1 when the pass mixes qubits above 11 (strided tile) */

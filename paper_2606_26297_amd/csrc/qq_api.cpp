@@ -64,6 +64,28 @@ bool g_prof = false;
 bool g_force_generic = false;  // QQ_GENERIC_PASSES=1: use the generic pass kernel everywhere
 std::vector<ProfRec> g_prof_log;
 
+// Event-timed record of one auxiliary launch (cost diagonal, probabilities, top-k, ...) when
+// profiling is on; `bytes` is the launch's algorithmic memory traffic.
+template <typename F>
+hipError_t prof_aux(int kind, int n, int diag_bytes, double bytes, hipStream_t stream, F launch)
+{
+    if (!g_prof) return launch();
+    ProfRec rec{};
+    hipError_t e;
+    if ((e = hipEventCreate(&rec.start)) != hipSuccess || (e = hipEventCreate(&rec.stop)) != hipSuccess) return e;
+    if ((e = hipEventRecord(rec.start, stream)) != hipSuccess) return e;
+    if ((e = launch()) != hipSuccess) return e;
+    if ((e = hipEventRecord(rec.stop, stream)) != hipSuccess) return e;
+    rec.meta.kind = kind;
+    rec.meta.pass_kind = -1;
+    rec.meta.n = n;
+    rec.meta.batch = 1;
+    rec.meta.diag_bytes = diag_bytes;
+    rec.meta.bytes = bytes;
+    g_prof_log.push_back(rec);
+    return hipSuccess;
+}
+
 struct DevBuf {
     void *p = nullptr;
     ~DevBuf()
@@ -114,6 +136,9 @@ struct qq_problem {
         double ms;
     };
     std::vector<Sched> sched;
+    // graphs captured on this problem: they hold its device pointers, so the problem is not
+    // destroyed and its allocation not replaced while any exists
+    int graphs = 0;
 
     ~qq_problem()
     {
@@ -1130,8 +1155,10 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
         QQ_HIP(hipMemcpyAsync(pb->d_pair_b, pb->pair_b.data(), sizeof(double) * np, hipMemcpyHostToDevice, stream));
         QQ_HIP(hipMemcpyAsync(pb->d_pair_bi, pb->pair_bi.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, stream));
     }
-    QQ_HIP(launch_cost_diag(n, pb->diag_type, pb->d_ell, pb->d_ell_i, np, pb->d_pair_ij, pb->d_pair_b, pb->d_pair_bi, c0,
-                            pb->c0_i, pb->d_diag, pb->dim, stream));
+    QQ_HIP(prof_aux(5, n, diag_bytes_of(pb->diag_type), (double)dbytes, stream, [&]() {
+        return launch_cost_diag(n, pb->diag_type, pb->d_ell, pb->d_ell_i, np, pb->d_pair_ij, pb->d_pair_b,
+                                pb->d_pair_bi, c0, pb->c0_i, pb->d_diag, pb->dim, stream);
+    }));
 
     // min / argmin / max of C
     const int nblk = (int)std::min<uint64_t>(1024, (pb->dim + 255) / 256);
@@ -1139,7 +1166,9 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
     QQ_HIP(hipMalloc(&part.p, (size_t)nblk * (2 * sizeof(double) + sizeof(uint64_t))));
     double *d_part = static_cast<double *>(part.p);
     uint64_t *d_idx = reinterpret_cast<uint64_t *>(d_part + 2 * nblk);
-    QQ_HIP(launch_minmax(pb->d_diag, pb->diag_type, pb->dim, d_part, d_idx, nblk, stream));
+    QQ_HIP(prof_aux(6, n, diag_bytes_of(pb->diag_type), (double)dbytes, stream, [&]() {
+        return launch_minmax(pb->d_diag, pb->diag_type, pb->dim, d_part, d_idx, nblk, stream);
+    }));
     std::vector<double> hp(2 * nblk);
     std::vector<uint64_t> hi(nblk);
     QQ_HIP(hipMemcpyAsync(hp.data(), d_part, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, stream));
@@ -1163,6 +1192,9 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
 
 qq_status qq_problem_destroy(qq_problem *prob)
 {
+    g_err.clear();
+    if (prob && prob->graphs > 0)
+        return fail(QQ_E_INVALID, "%d captured graph(s) still use this problem; destroy them first", prob->graphs);
     delete prob;
     return QQ_OK;
 }
@@ -1233,6 +1265,9 @@ qq_status qq_set_allocation(qq_problem *pb, int M, const int32_t *qpu_of_var, co
                             int64_t *cross_out, int64_t *remote_out)
 {
     if (!pb || !qpu_of_var) return fail(QQ_E_INVALID, "NULL argument");
+    if (pb->graphs > 0)
+        return fail(QQ_E_INVALID, "%d captured graph(s) use this problem's current allocation; destroy them first",
+                    pb->graphs);
     const int n = pb->n;
     if (M < 1 || M > QQ_MAX_QPUS) return fail(QQ_E_INVALID, "num_qpus = %d outside [1, %d]", M, QQ_MAX_QPUS);
     std::vector<int> count(M, 0);
@@ -1424,13 +1459,17 @@ qq_status qq_probabilities(qq_problem *pb, int p, const double *params, int flag
     if (qq_status st = state_into(pb, p, params, flags, stream, own, L); st != QQ_OK) return st;
     const void *psi = static_cast<char *>(own.p) + L.psi;
     if (flags & QQ_OUT_ON_DEVICE) {
-        QQ_HIP(launch_probabilities(psi, flags & QQ_C128, pb->dim, prob_out, stream));
+        QQ_HIP(prof_aux(7, pb->n, 0, (double)pb->dim * (((flags & QQ_C128) ? 16 : 8) + 8), stream, [&]() {
+            return launch_probabilities(psi, flags & QQ_C128, pb->dim, prob_out, stream);
+        }));
         QQ_HIP(hipStreamSynchronize(stream));
         return QQ_OK;
     }
     DevBuf tmp;
     if (hipMalloc(&tmp.p, (size_t)pb->dim * sizeof(double)) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc failed");
-    QQ_HIP(launch_probabilities(psi, flags & QQ_C128, pb->dim, static_cast<double *>(tmp.p), stream));
+    QQ_HIP(prof_aux(7, pb->n, 0, (double)pb->dim * (((flags & QQ_C128) ? 16 : 8) + 8), stream, [&]() {
+        return launch_probabilities(psi, flags & QQ_C128, pb->dim, static_cast<double *>(tmp.p), stream);
+    }));
     QQ_HIP(hipMemcpyAsync(prob_out, tmp.p, (size_t)pb->dim * sizeof(double), hipMemcpyDeviceToHost, stream));
     QQ_HIP(hipStreamSynchronize(stream));
     return QQ_OK;
@@ -1456,8 +1495,10 @@ qq_status qq_topk(qq_problem *pb, int p, const double *params, int flags, int k,
     uint64_t *d_idx = reinterpret_cast<uint64_t *>(sc + (size_t)nblocks * k * 16);
     double *d_prob = reinterpret_cast<double *>(d_idx + k);
     double *d_cost = d_prob + k;
-    QQ_HIP(launch_topk(psi, flags & QQ_C128, pb->dim, k, pb->d_diag, pb->diag_type, d_idx, d_prob, d_cost, sc, nblocks,
-                       stream));
+    QQ_HIP(prof_aux(8, pb->n, 0, (double)pb->dim * ((flags & QQ_C128) ? 16 : 8), stream, [&]() {
+        return launch_topk(psi, flags & QQ_C128, pb->dim, k, pb->d_diag, pb->diag_type, d_idx, d_prob, d_cost, sc,
+                           nblocks, stream);
+    }));
     std::vector<uint64_t> hi(k);
     std::vector<double> hp(k), hc(k);
     QQ_HIP(hipMemcpyAsync(hi.data(), d_idx, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, stream));
@@ -1685,6 +1726,7 @@ qq_status qq_graph_create(qq_problem *pb, int p, int batch, int flags, const dou
     if (st != QQ_OK) return fail(st, "capturing the step failed: %s", err.c_str());
     if (ec != hipSuccess) return fail(QQ_E_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
     QQ_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    ++pb->graphs;
     *out = g.release();
     return QQ_OK;
 }
@@ -1739,6 +1781,7 @@ qq_status qq_graph_read(qq_graph *g, double *energy, double *grad, double *histo
 
 qq_status qq_graph_destroy(qq_graph *g)
 {
+    if (g && g->exec) --g->pb->graphs;  // counted once instantiated
     delete g;
     return QQ_OK;
 }

@@ -432,6 +432,7 @@ def qq_profile_read(max_records: int = 1 << 16):
 
 PASS_KIND_NAMES = ["FK_FIRST", "FK_MID", "FK_TURN", "FK_LAST", "FK_LASTG", "FK_BMID", "FK_BTURN", "FK_BLAST"]
 DIAG_TYPE_NAMES = {8: "double", 4: "int", 2: "short"}
+AUX_KIND_NAMES = {5: "cost_diag_kernel", 6: "minmax_kernel", 7: "prob_kernel", 8: "topk_stage1+2"}
 
 
 def kernel_name(rec) -> str:
@@ -440,6 +441,8 @@ def kernel_name(rec) -> str:
         return "finalize_kernel"
     if rec["kind"] == 4:
         return f"many_kernel<{DIAG_TYPE_NAMES[rec['diag_bytes']]}>"
+    if rec["kind"] in AUX_KIND_NAMES:
+        return AUX_KIND_NAMES[rec["kind"]]
     dt = DIAG_TYPE_NAMES[rec["diag_bytes"]]
     if rec["pass_kind"] >= 0:
         tf = lambda x: "true" if x else "false"  # noqa: E731

@@ -154,3 +154,23 @@ def test_graph_validation():
             N.qq_graph_run(g, -1)
     finally:
         N.qq_graph_destroy(g)
+
+
+def test_problem_is_kept_while_a_graph_uses_it():
+    import torch
+
+    inst = W.regular_graph_qubo(14, 81)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    xt = torch.tensor(W.random_params(2, 2, 82), device="cuda:0")
+    g = N.qq_graph_create(pb.handle, 2, 2, 0, None, xt)
+    with pytest.raises(N.QQError) as ei:
+        N.qq_problem_destroy(pb.handle)
+    assert ei.value.status == N.QQ_E_INVALID
+    with pytest.raises(N.QQError) as ei:
+        pb.set_allocation(np.array([0] * 7 + [1] * 7), 2)
+    assert ei.value.status == N.QQ_E_INVALID
+    N.qq_graph_run(g, 2)
+    N.qq_graph_destroy(g)
+    pb.set_allocation(np.array([0] * 7 + [1] * 7), 2)
+    pb.close()
+    assert pb.handle is None
