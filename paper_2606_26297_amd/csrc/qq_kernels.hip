@@ -335,14 +335,28 @@ __global__ void __launch_bounds__(256) minmax_kernel(const DT *d, uint64_t dim, 
     __shared__ uint64_t sidx[256];
     double mn = INFINITY, mx = -INFINITY;
     uint64_t mi = ~0ull;
+    // kUnroll coalesced loads in flight per thread, then the comparisons in increasing z (so the
+    // first index of a tie within the thread is kept)
+    constexpr int kUnroll = 8;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) {
-        const double c = (double)d[z];
-        if (c < mn) {
-            mn = c;
-            mi = z;
+    for (uint64_t z0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z0 < dim; z0 += stride * kUnroll) {
+        double c[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t z = z0 + u * stride;
+            c[u] = z < dim ? (double)d[z] : INFINITY;
         }
-        mx = fmax(mx, c);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t z = z0 + u * stride;
+            if (z < dim) {
+                if (c[u] < mn) {
+                    mn = c[u];
+                    mi = z;
+                }
+                mx = fmax(mx, c[u]);
+            }
+        }
     }
     const int t = threadIdx.x;
     smin[t] = mn;
@@ -505,10 +519,25 @@ __global__ void __launch_bounds__(256) topk_stage1(const C2 *psi, uint64_t dim, 
 {
     TopList L;
     L.init();
+    // kUnroll coalesced loads in flight per thread before the insertions (the ranking by
+    // (probability, index) does not depend on the insertion order)
+    constexpr int kUnroll = 8;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) {
-        const double re = (double)psi[z].x, im = (double)psi[z].y;
-        L.insert(fma(re, re, im * im), z);
+    for (uint64_t z0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z0 < dim; z0 += stride * kUnroll) {
+        C2 v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t z = z0 + u * stride;
+            if (z < dim) v[u] = psi[z];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t z = z0 + u * stride;
+            if (z < dim) {
+                const double re = (double)v[u].x, im = (double)v[u].y;
+                L.insert(fma(re, re, im * im), z);
+            }
+        }
     }
     tournament(L, k, cp + (size_t)blockIdx.x * k, ci + (size_t)blockIdx.x * k);
 }
