@@ -4,9 +4,10 @@ Workload (one "step"): the 28-node random 3-regular QUBO (edge weights U[0,1],
 linear terms N(0, 0.5^2), seeded), p = 8, 64 multi-start parameter sets drawn
 U[0, pi]; one step evaluates J(x) and all 16 partial derivatives for every
 start through the C ABI (qq_evaluate, QQ_GRAD, device-resident params and
-outputs), in waves of `--wave` starts (default 32: measured faster per byte on
-MI355X than 16, and 128 GiB of states per wave fits the 288 GB with room to
-spare).  Inputs are resident in HBM before the
+outputs), in waves of `--wave` starts (default 64, all starts in one call: the
+widest batch measured fastest per byte on MI355X, 16 -> 32 -> 64 giving 23.0 ->
+24.7 -> 25.9 evaluations/s; its 256 GiB of psi and lambda fit the 288 GB HBM).
+Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
 Before timing, the schedule of that evaluation (workgroups per state, pairing of
@@ -254,7 +255,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--wave", type=int, default=32, help="starts per qq_evaluate call")
+    ap.add_argument("--wave", type=int, default=64, help="starts per qq_evaluate call")
     ap.add_argument("--starts", type=int, default=64)
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--p", type=int, default=8)
@@ -265,8 +266,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch measurement")
     ap.add_argument("--no-multi-qpu", action="store_true", help="skip the n = 32 multi-QPU measurement")
-    ap.add_argument("--schedule", default=None, metavar="G:PAIRING",
-                    help="pin this schedule (workgroups per state, set pairing) instead of autotuning")
+    ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER]",
+                    help="pin this schedule (workgroups per state, set pairing, tile order) instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (reference kernel for the traffic counters)")
     args = ap.parse_args()
@@ -300,8 +301,10 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     if args.schedule:
-        G, pairing = (int(v) for v in args.schedule.split(":"))
-        N.qq_set_schedule(pb.handle, p, B, flags, {"workgroups_per_state": G, "set_pairing": pairing})
+        fields = [int(v) for v in args.schedule.split(":")]
+        G, pairing, order = (fields + [0, 0])[:3]
+        N.qq_set_schedule(pb.handle, p, B, flags, {"workgroups_per_state": G, "set_pairing": pairing,
+                                                   "tile_order": order})
     schedule = N.qq_get_schedule(pb.handle, p, B, flags)
     if not args.no_autotune and not args.schedule:
         progress("autotuning the schedule")
@@ -368,6 +371,10 @@ def main():
            "algorithmic_bytes_per_eval": step_bytes / S,
            "roofline": roofline, "kernels": kernels}
 
+    # the other legs allocate their own memory: release the timed workspace first
+    del ws
+    torch.cuda.empty_cache()
+
     if args.copy_calibration:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
         # counter-derived HBM traffic of the pass kernels
@@ -399,7 +406,6 @@ def main():
                              "speedup": round(value * tp, 2),
                              "definition": "complex128, one kernel per gate (phase per layer, RX per qubit and "
                                            "layer, energy reduction, unfused adjoint), one parameter set per call"}
-    del ws
     pb.close()
     torch.cuda.empty_cache()
     progress("cost diagonal, probabilities, top-k")

@@ -244,9 +244,12 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
  * qq_set_schedule pins one (NULL restores the default); qq_get_schedule reports
  * the one in force.  qq_workspace_size, qq_evaluate and qq_graph_create use it.
  *
- * qq_autotune times every candidate (G of the default, half and double it,
- * times every pairing that applies) with HIP events on seeded parameter sets
- * (one warm-up, median of three), pins the fastest and, if cache_path is not
+ * qq_autotune times every candidate with HIP events on seeded parameter sets
+ * (one warm-up, then the median of three runs, or one run when the warm-up
+ * took over 200 ms): G of the default, half and double it, times
+ * every pairing that applies, in the strided tile order; then the blocked tile
+ * order at the best pairing for the best G, half and double it.  It pins the
+ * fastest and, if cache_path is not
  * NULL, appends it to that JSON-lines file; an entry already there for the same
  * device, n, p, batch, planning flags and diagonal width is used without timing.
  * qq_autotune_many does the same for qq_evaluate_many over tiles_per_chunk in
@@ -262,6 +265,8 @@ typedef struct {
     int pinned;       /* 1 when a schedule is pinned for the key */
     int from_cache;   /* 1 when qq_autotune read it from the cache file */
     int tried;        /* candidates timed by qq_autotune */
+    int tile_order;   /* 0: workgroup g takes tiles g, g + G, ... (neighbouring tiles run together);
+                         1: workgroup g takes a contiguous range of tiles (specialised kernels only) */
 } qq_schedule;
 
 qq_status qq_set_schedule(qq_problem *prob, int p, int batch, int flags, const qq_schedule *schedule);

@@ -132,7 +132,7 @@ struct qq_problem {
     PartDesc *d_part = nullptr;
     // schedules pinned by qq_set_schedule / qq_autotune, keyed by (p, batch, planning flags)
     struct Sched {
-        int p, batch, flags, G, pairing;
+        int p, batch, flags, G, pairing, blocked;
         double ms;
     };
     std::vector<Sched> sched;
@@ -399,6 +399,7 @@ int choose_G(int n, int B)
 struct Layout {
     size_t psi = 0, lam = 0, partial = 0, params = 0, out = 0, total = 0;
     int G = 1;
+    int blocked = 0;  // tile order of the specialised kernels
     int nslots = 0;
 };
 
@@ -456,7 +457,9 @@ Plan plan_for(const qq_problem *pb, int p, int batch, int flags, bool store)
 Layout layout_for(const qq_problem *pb, int p, int batch, int flags, const Plan &plan)
 {
     const auto *e = find_sched(pb, p, batch, flags);
-    return make_layout(pb, p, batch, flags, plan, e ? e->G : 0);
+    Layout L = make_layout(pb, p, batch, flags, plan, e ? e->G : 0);
+    L.blocked = e ? e->blocked : 0;
+    return L;
 }
 
 qq_status check_params_host(const double *params, size_t count)
@@ -550,6 +553,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
         }
         if (use_fast && pp.fkind >= 0) {
             FastPassParams fp;
+            fp.blocked = L.blocked;
             fp.part = (flags & QQ_PARTITIONED) ? 1 : 0;
             fp.part_desc = pb->d_part;
             fp.part_tables = pb->d_tables;
@@ -811,17 +815,25 @@ qq_status cache_append(const char *path, const std::string &line)
     return QQ_OK;
 }
 
-// Median of three timed runs of `run` after one warm-up, in ms.
+// Median of three timed runs of `run` after a timed warm-up, in ms; a single run when the
+// warm-up took over 200 ms (timing noise is then small against the run, and the tuning
+// of a large evaluation stays within a minute or two).
 template <typename F>
 qq_status time_median(hipStream_t stream, F run, double &ms)
 {
-    if (qq_status st = run(); st != QQ_OK) return st;
     hipEvent_t a, b;
     QQ_HIP(hipEventCreate(&a));
     QQ_HIP(hipEventCreate(&b));
-    double t[3];
+    float warm = 0.0f;
     qq_status st = QQ_OK;
-    for (int r = 0; r < 3 && st == QQ_OK; ++r) {
+    if (hipEventRecord(a, stream) != hipSuccess) st = fail(QQ_E_DEVICE, "hipEventRecord failed");
+    if (st == QQ_OK) st = run();
+    if (st == QQ_OK && (hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                        hipEventElapsedTime(&warm, a, b) != hipSuccess))
+        st = fail(QQ_E_DEVICE, "event timing failed");
+    const int reps = warm > 200.0f ? 1 : 3;
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int r = 0; r < reps && st == QQ_OK; ++r) {
         float f = 0.0f;
         if (hipEventRecord(a, stream) != hipSuccess) st = fail(QQ_E_DEVICE, "hipEventRecord failed");
         if (st == QQ_OK) st = run();
@@ -833,22 +845,23 @@ qq_status time_median(hipStream_t stream, F run, double &ms)
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (st != QQ_OK) return st;
-    std::sort(t, t + 3);
-    ms = t[1];
+    std::sort(t, t + reps);
+    ms = t[reps / 2];
     return QQ_OK;
 }
 
-void pin_sched(qq_problem *pb, int p, int batch, int flags, int G, int pairing, double ms)
+void pin_sched(qq_problem *pb, int p, int batch, int flags, int G, int pairing, int blocked, double ms)
 {
     const int sf = sched_flags(flags);
     for (auto &e : pb->sched)
         if (e.p == p && e.batch == batch && e.flags == sf) {
             e.G = G;
             e.pairing = pairing;
+            e.blocked = blocked;
             e.ms = ms;
             return;
         }
-    pb->sched.push_back({p, batch, sf, G, pairing, ms});
+    pb->sched.push_back({p, batch, sf, G, pairing, blocked, ms});
 }
 
 uint64_t fnv1a(uint64_t h, int64_t v)
@@ -1807,7 +1820,9 @@ qq_status qq_set_schedule(qq_problem *pb, int p, int batch, int flags, const qq_
     if (sch->set_pairing < 0 || sch->set_pairing >= kPairings || (sch->set_pairing != 0 && !pairing_applies(pb->n)))
         return fail(QQ_E_INVALID, "set_pairing = %d is not available at n = %d", sch->set_pairing, pb->n);
     if ((size_t)batch * (size_t)G > 0x7fffffffull) return fail(QQ_E_INVALID, "batch * workgroups_per_state too large");
-    pin_sched(pb, p, batch, flags, G, sch->set_pairing, sch->ms);
+    if (sch->tile_order != 0 && sch->tile_order != 1)
+        return fail(QQ_E_INVALID, "tile_order = %d must be 0 (strided) or 1 (blocked)", sch->tile_order);
+    pin_sched(pb, p, batch, flags, G, sch->set_pairing, sch->tile_order, sch->ms);
     return QQ_OK;
 }
 
@@ -1820,6 +1835,7 @@ qq_status qq_get_schedule(const qq_problem *pb, int p, int batch, int flags, qq_
     if (const auto *e = find_sched(pb, p, batch, flags)) {
         out->workgroups_per_state = e->G;
         out->set_pairing = e->pairing;
+        out->tile_order = e->blocked;
         out->ms = e->ms;
         out->pinned = 1;
     } else {
@@ -1845,9 +1861,10 @@ qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *c
     const std::string key(keybuf);
     std::string line;
     if (cache_lookup(cache_path, key, line)) {
-        double G = 0, pr = 0, ms = 0;
-        if (json_num(line, "G", G) && json_num(line, "pairing", pr) && json_num(line, "ms", ms)) {
-            qq_schedule s{(int)G, (int)pr, ms, 1, 1, 0};
+        double G = 0, pr = 0, ms = 0, order = 0;
+        if (json_num(line, "G", G) && json_num(line, "pairing", pr) && json_num(line, "ms", ms) &&
+            json_num(line, "tile_order", order)) {
+            qq_schedule s{(int)G, (int)pr, ms, 1, 1, 0, (int)order};
             if (qq_status st = qq_set_schedule(pb, p, batch, flags, &s); st == QQ_OK) {
                 *out = s;
                 return QQ_OK;
@@ -1855,18 +1872,23 @@ qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *c
             g_err.clear();  // a stale entry: tune again
         }
     }
-    // candidates: the heuristic G, half and double it; every pairing where it applies
+    // stage 1: the heuristic G, half and double it, times every pairing where it applies (strided
+    // tile order); stage 2: the blocked tile order at the best pairing, for the best G, half and double
     const uint64_t T = tiles_per_state(pb->n);
     const int G0 = choose_G(pb->n, batch);
-    std::vector<int> Gs;
-    for (int G : {G0 / 2, G0, G0 * 2})
-        if (G >= 1 && (uint64_t)G <= T && (size_t)batch * G <= 0x7fffffffull) Gs.push_back(G);
+    auto g_candidates = [&](int Gc) {
+        std::vector<int> v;
+        for (int G : {Gc / 2, Gc, Gc * 2})
+            if (G >= 1 && (uint64_t)G <= T && (size_t)batch * G <= 0x7fffffffull) v.push_back(G);
+        return v;
+    };
+    const std::vector<int> Gs = g_candidates(G0);
     const int npair = pairing_applies(pb->n) ? kPairings : 1;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     QQ_HIP(hipSetDevice(pb->device));
     size_t need = 0;
     const Plan plan0 = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false), 0);
-    for (int G : Gs) need = std::max(need, make_layout(pb, p, batch, flags, plan0, G).total);
+    for (int G : g_candidates(G0 * 2)) need = std::max(need, make_layout(pb, p, batch, flags, plan0, G).total);
     if (qq_status st = check_device_fits(pb->device, need, "the tuning workspace"); st != QQ_OK) return st;
     DevBuf ws, dx;
     if (hipMalloc(&ws.p, need) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) for tuning failed", need);
@@ -1875,30 +1897,41 @@ qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *c
     QQ_HIP(hipMemcpy(dx.p, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice));
     const int eflags = flags | QQ_PARAMS_ON_DEVICE;
     double best = INFINITY;
-    int bestG = G0, bestP = 0, tried = 0;
-    for (int pr = 0; pr < npair; ++pr) {
+    int bestG = G0, bestP = 0, bestO = 0, tried = 0;
+    auto time_one = [&](int pr, int G, int order) -> qq_status {
         const Plan plan = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false), pr);
-        for (int G : Gs) {
-            const Layout L = make_layout(pb, p, batch, flags, plan, G);
-            double ms = 0;
-            auto run = [&]() {
-                return run_plan(pb, plan, L, p, batch, eflags, static_cast<char *>(ws.p),
-                                static_cast<const double *>(dx.p), stream, true);
-            };
-            if (qq_status st = time_median(stream, run, ms); st != QQ_OK) return st;
-            ++tried;
-            if (ms < best) {
-                best = ms;
-                bestG = G;
-                bestP = pr;
-            }
+        Layout L = make_layout(pb, p, batch, flags, plan, G);
+        L.blocked = order;
+        double ms = 0;
+        auto run = [&]() {
+            return run_plan(pb, plan, L, p, batch, eflags, static_cast<char *>(ws.p), static_cast<const double *>(dx.p),
+                            stream, true);
+        };
+        if (qq_status st = time_median(stream, run, ms); st != QQ_OK) return st;
+        ++tried;
+        if (ms < best) {
+            best = ms;
+            bestG = G;
+            bestP = pr;
+            bestO = order;
         }
+        return QQ_OK;
+    };
+    for (int pr = 0; pr < npair; ++pr)
+        for (int G : Gs)
+            if (qq_status st = time_one(pr, G, 0); st != QQ_OK) return st;
+    const bool multi_pass = make_sets(pb->n, 0).size() > 1 && !(flags & QQ_C128) && pb->n <= kFastMaxN;
+    if (multi_pass) {  // the tile order only applies to the specialised multi-pass kernels
+        const int pr = bestP;
+        for (int G : g_candidates(bestG))
+            if (qq_status st = time_one(pr, G, 1); st != QQ_OK) return st;
     }
-    pin_sched(pb, p, batch, flags, bestG, bestP, best);
-    char tail[160];
-    std::snprintf(tail, sizeof tail, "\"G\":%d,\"pairing\":%d,\"ms\":%.4f}", bestG, bestP, best);
+    pin_sched(pb, p, batch, flags, bestG, bestP, bestO, best);
+    char tail[200];
+    std::snprintf(tail, sizeof tail, "\"G\":%d,\"pairing\":%d,\"tile_order\":%d,\"ms\":%.4f}", bestG, bestP, bestO,
+                  best);
     if (qq_status st = cache_append(cache_path, key + tail); st != QQ_OK) return st;
-    *out = qq_schedule{bestG, bestP, best, 1, 0, tried};
+    *out = qq_schedule{bestG, bestP, best, 1, 0, tried, bestO};
     return QQ_OK;
 }
 

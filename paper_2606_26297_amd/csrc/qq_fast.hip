@@ -165,6 +165,7 @@ hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassPa
     a.lam = static_cast<float2 *>(pp.lam);
     a.state_stride = pp.state_stride;
     a.partial = pp.partial;
+    a.blocked = pp.blocked;
     a.part = pp.part_desc;
     a.tables = pp.part_tables;
     a.cross = pp.cross_diag;

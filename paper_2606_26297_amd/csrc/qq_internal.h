@@ -133,6 +133,7 @@ hipError_t launch_local_tables(int n, int diag_type, const PartDesc *d_pd, const
 // Specialised complex64 pass kernels (qq_fast.hip): one kernel per pass kind.
 enum FastPassKind : int { FK_FIRST = 0, FK_MID, FK_TURN, FK_LAST, FK_LASTG, FK_BMID, FK_BTURN, FK_BLAST, FK_SINGLE };
 struct FastPassParams {
+    int blocked;  // tile order: 0 strided (tiles g, g + G, ...), 1 blocked (contiguous range per workgroup)
     int part;  // 1: the phase is the product of the per-QPU local factors and the cross factor
     const PartDesc *part_desc;  // device
     const void *part_tables;

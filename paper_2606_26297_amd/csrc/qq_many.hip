@@ -238,6 +238,7 @@ __device__ __forceinline__ void run_chunk(const ManyInst &I, const ManyPass &P, 
     a.lam = static_cast<float2 *>(I.lam);
     a.state_stride = I.dim_mask + 1;
     a.partial = nullptr;
+    a.blocked = 0;
     a.part = nullptr;
     a.tables = nullptr;
     a.cross = nullptr;

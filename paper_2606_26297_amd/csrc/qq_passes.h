@@ -354,6 +354,7 @@ struct FastArgs {
     float2 *lam;
     uint64_t state_stride;
     double *partial;
+    int blocked;           // 0: tiles g, g + G, ... ; 1: tiles [g T/G, (g + 1) T/G) (T a multiple of G)
     const PartDesc *part;  // partitioned phases (PART bodies only)
     const void *tables;    // packed per-QPU local tables
     const void *cross;     // cross-QPU diagonal, 2^n entries
@@ -503,7 +504,16 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
     const uint64_t diag_a = (uint64_t)a.diag;
     float2 v[NS][kRegs];
 
-    for (uint64_t tile = g; tile < a.tiles; tile += a.G) {
+    // tile order: strided (workgroups that run together take neighbouring tiles) or blocked
+    // (each workgroup takes a contiguous range, so concurrently running ones are far apart)
+    uint64_t t_begin = (uint64_t)g, t_end = a.tiles, t_step = (uint64_t)a.G;
+    if (a.blocked) {
+        const uint64_t per = a.tiles / (uint64_t)a.G;
+        t_begin = (uint64_t)g * per;
+        t_end = t_begin + per;
+        t_step = 1;
+    }
+    for (uint64_t tile = t_begin; tile < t_end; tile += t_step) {
         uint64_t base;
         if constexpr (HIGH) base = tile_base(tile, a.pos4, a.pos8, a.w1, a.w2);
         else base = tile << kTileBits;

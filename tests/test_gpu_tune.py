@@ -1,7 +1,7 @@
 """GPU tests of pinned schedules and the autotuner (through the C ABI).
 
-* workgroups per state only changes which workgroup takes which tile: results
-  agree to 1e-12 relative (order of the FP64 partial sums);
+* workgroups per state and the tile order only change which workgroup takes
+  which tile: results agree to 1e-12 relative (order of the FP64 partial sums);
 * the set pairing changes which qubits share a pass, hence the complex64
   rounding: every pairing is checked against the closed form of a separable
   n = 28 problem (1e-5 relative);
@@ -37,17 +37,19 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-def test_workgroups_per_state_only_reorders_sums():
+def test_workgroups_per_state_and_tile_order_only_reorder_sums():
     inst = W.regular_graph_qubo(20, 51)
     pb = Problem(inst.H, inst.f, inst.c0)
     p, B = 3, 4
     x = W.random_params(p, B, 52)
     e0, g0 = pb.evaluate(x, grad=True)
     for G in (1, 2, 64, 256):
-        N.qq_set_schedule(pb.handle, p, B, GRAD, {"workgroups_per_state": G})
-        assert N.qq_get_schedule(pb.handle, p, B, GRAD)["workgroups_per_state"] == G
-        e, g = pb.evaluate(x, grad=True)
-        assert rel(e, e0) <= 1e-12 and rel(g, g0) <= 1e-12, G
+        for order in (0, 1):
+            N.qq_set_schedule(pb.handle, p, B, GRAD, {"workgroups_per_state": G, "tile_order": order})
+            got = N.qq_get_schedule(pb.handle, p, B, GRAD)
+            assert got["workgroups_per_state"] == G and got["tile_order"] == order
+            e, g = pb.evaluate(x, grad=True)
+            assert rel(e, e0) <= 1e-12 and rel(g, g0) <= 1e-12, (G, order)
     N.qq_set_schedule(pb.handle, p, B, GRAD, None)
     assert N.qq_get_schedule(pb.handle, p, B, GRAD)["pinned"] == 0
 
@@ -79,7 +81,8 @@ def test_invalid_schedules_are_rejected():
     inst = W.regular_graph_qubo(20, 55)
     pb = Problem(inst.H, inst.f, inst.c0)
     for bad in ({"workgroups_per_state": 3}, {"workgroups_per_state": 512}, {"workgroups_per_state": 0},
-                {"workgroups_per_state": 4, "set_pairing": 1}, {"workgroups_per_state": 4, "set_pairing": 3}):
+                {"workgroups_per_state": 4, "set_pairing": 1}, {"workgroups_per_state": 4, "set_pairing": 3},
+                {"workgroups_per_state": 4, "tile_order": 2}):
         with pytest.raises(N.QQError) as ei:
             N.qq_set_schedule(pb.handle, 2, 2, GRAD, bad)
         assert ei.value.status == N.QQ_E_INVALID, bad
