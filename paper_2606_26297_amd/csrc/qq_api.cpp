@@ -119,6 +119,10 @@ struct qq_problem {
     int32_t *d_pair_ij = nullptr;
     double *d_pair_b = nullptr;
     int32_t *d_pair_bi = nullptr;
+    // Couplings among four consecutive qubits R_j = q + j, for the register-cost reconstruction of
+    // the pass kernels: regq[16 q + r] = sum over the bits k > j of r of b_{R_j R_k}, j the lowest
+    // bit of r (0 for r = 0 and single bits); q = 0 .. n - 4.
+    double *d_regq = nullptr;
     // summary
     double alpha = 0, sigma_c = 0, cmin = 0, cmax = 0;
     uint64_t argmin = 0;
@@ -142,7 +146,7 @@ struct qq_problem {
 
     ~qq_problem()
     {
-        void *ptrs[] = {d_diag, d_ell, d_ell_i, d_pair_ij, d_pair_b, d_pair_bi, d_qpu, d_tables, d_cross, d_part};
+        void *ptrs[] = {d_diag, d_ell, d_ell_i, d_pair_ij, d_pair_b, d_pair_bi, d_regq, d_qpu, d_tables, d_cross, d_part};
         if (dim) (void)hipSetDevice(device);
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
@@ -483,7 +487,7 @@ qq_status check_device_fits(int device, size_t bytes, const char *what)
 // plus one cost-diagonal read per operation that needs C(z) -- counted once per
 // launch, since every state of the batch reads the same diagonal entries (the
 // partitioned phase also reads the cross-QPU diagonal).
-double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128)
+double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128, bool fast)
 {
     const double es = c128 ? 16.0 : 8.0, d = diag_bytes_of(pb->diag_type);
     int moves = 0;
@@ -491,13 +495,18 @@ double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128)
     if (pp.flags & PF_LOAD_LAM) ++moves;
     if (pp.flags & PF_STORE_PSI) ++moves;
     if (pp.flags & PF_STORE_LAM) ++moves;
-    double diag_reads = 0;
+    // reads of the cost diagonal and of the cross-QPU diagonal (a partitioned phase reads the
+    // cross diagonal and the small local tables instead of the cost diagonal)
+    double diag_reads = 0, cross_reads = 0;
     for (const Op &o : pp.ops) {
-        if (o.kind == OP_PHASE || o.kind == OP_ENERGY || o.kind == OP_ENERGY_LAMBDA || o.kind == OP_GGAMMA) diag_reads += 1;
-        if ((o.kind == OP_PHASE || (o.kind == OP_GGAMMA && (o.flags & OPF_UNPHASE))) && (o.flags & OPF_PARTITIONED))
+        const bool part = (o.flags & OPF_PARTITIONED) != 0;
+        if ((o.kind == OP_PHASE && !part) || o.kind == OP_ENERGY || o.kind == OP_ENERGY_LAMBDA || o.kind == OP_GGAMMA)
             diag_reads += 1;
+        if ((o.kind == OP_PHASE || (o.kind == OP_GGAMMA && (o.flags & OPF_UNPHASE))) && part) cross_reads += 1;
     }
-    return (double)pb->dim * (B * moves * es + diag_reads * d);
+    // the specialised kernels read 5 of every 16 diagonal entries and form the rest from them
+    if (fast) diag_reads *= 5.0 / 16.0;
+    return (double)pb->dim * (B * moves * es + (diag_reads + cross_reads) * d);
 }
 
 // Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
@@ -579,6 +588,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             fp.lam = a.lam;
             fp.state_stride = pb->dim;
             fp.partial = a.partial;
+            fp.cq = pb->d_regq + 16 * (pp.fkind == FK_FIRST ? sd.pos8 : sd.pos4);
             QQ_HIP(launch_fast_pass(pp.fkind, sd.high != 0, pb->diag_type, fp, stream));
         } else {
             QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
@@ -595,7 +605,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             rec.meta.c128 = c128;
             rec.meta.n = pb->n;
             rec.meta.batch = B;
-            rec.meta.bytes = pass_bytes(pb, pp, B, c128);
+            rec.meta.bytes = pass_bytes(pb, pp, B, c128, use_fast && pp.fkind >= 0);
             g_prof_log.push_back(rec);
         }
         slot_base += a.nslots;
@@ -981,7 +991,7 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
                     slot_base += P.nslots;
                     for (int o : pp.slot_out) G.slot_out.push_back((uint16_t)o);
                     G.pass.push_back(P);
-                    G.bytes += pass_bytes(pb, pp, I.B, false);
+                    G.bytes += pass_bytes(pb, pp, I.B, false, true);
                 }
                 I.nslots = slot_base;
                 const size_t sb = (size_t)pb->dim * sizeof(float2) * I.B;
@@ -1161,6 +1171,19 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
     QQ_HIP(hipMalloc((void **)&pb->d_pair_ij, sizeof(int32_t) * std::max(2, 2 * np)));
     QQ_HIP(hipMalloc((void **)&pb->d_pair_b, sizeof(double) * std::max(1, np)));
     QQ_HIP(hipMalloc((void **)&pb->d_pair_bi, sizeof(int32_t) * std::max(1, np)));
+    {
+        std::vector<double> regq(16 * (size_t)std::max(1, n - 3), 0.0);
+        for (int q = 0; q + 4 <= n; ++q)
+            for (int r = 1; r < 16; ++r) {
+                const int j = __builtin_ctz(r);
+                double sum = 0.0;
+                for (int k = j + 1; k < 4; ++k)
+                    if ((r >> k) & 1) sum += pb->b[(size_t)(q + j) * n + (q + k)];
+                regq[16 * (size_t)q + r] = sum;
+            }
+        QQ_HIP(hipMalloc((void **)&pb->d_regq, sizeof(double) * regq.size()));
+        QQ_HIP(hipMemcpy(pb->d_regq, regq.data(), sizeof(double) * regq.size(), hipMemcpyHostToDevice));
+    }
     QQ_HIP(hipMemcpyAsync(pb->d_ell, pb->ell.data(), sizeof(double) * n, hipMemcpyHostToDevice, stream));
     QQ_HIP(hipMemcpyAsync(pb->d_ell_i, pb->ell_i.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
     if (np) {
@@ -1591,6 +1614,7 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
             I.params = (flags & QQ_PARAMS_ON_DEVICE) ? params[i]
                                                      : reinterpret_cast<const double *>(ws + M.params) + M.param_off[i];
             I.diag = problems[i]->d_diag;
+            I.regq = problems[i]->d_regq;
             if (I.npasses > 1 || G.pass[I.pass_off].kind != FK_SINGLE) {
                 I.psi = ws + G.states + reinterpret_cast<size_t>(I.psi);
                 I.lam = grad ? ws + G.states + reinterpret_cast<size_t>(I.lam) : nullptr;

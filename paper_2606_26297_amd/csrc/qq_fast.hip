@@ -169,6 +169,7 @@ hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassPa
     a.part = pp.part_desc;
     a.tables = pp.part_tables;
     a.cross = pp.cross_diag;
+    a.cq = pp.cq;
     const bool part = pp.part != 0;
     switch (kind) {
     case FK_FIRST: return launch_kind<FK_FIRST>(a, high, diag_type, part, s);

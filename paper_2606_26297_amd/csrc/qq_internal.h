@@ -149,6 +149,9 @@ struct FastPassParams {
     void *lam;
     uint64_t state_stride;
     double *partial;
+    // device [16]: sums of the couplings among the register qubits of the layout in which the pass
+    // reads the diagonal (regq of the problem at that layout's register run)
+    const double *cq;
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
 
@@ -168,6 +171,7 @@ struct ManyInst {
     double amp0, escale;
     const double *params;   // device [B][2p]
     const void *diag;
+    const double *regq;     // device [n - 3][16]: register-run coupling sums (see qq_problem::regq)
     void *psi, *lam;        // device [B][2^n] complex64 (multi-pass problems)
     double *energy_out;     // device [B], or NULL: results go to out_ws
     double *grad_out;       // device [B][2p] (with energy_out)

@@ -242,6 +242,7 @@ __device__ __forceinline__ void run_chunk(const ManyInst &I, const ManyPass &P, 
     a.part = nullptr;
     a.tables = nullptr;
     a.cross = nullptr;
+    a.cq = I.regq + 16 * (P.kind == FK_FIRST ? P.pos8 : P.pos4);
     double acc[3] = {0.0, 0.0, 0.0};
     const int g = (int)t0;
     switch (P.kind) {

@@ -80,6 +80,38 @@ __device__ __forceinline__ uint64_t opaque_u64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Cost values of a thread's 16 registers from five loads of the diagonal.  C is quadratic in the
+// bits of z (eq. (6)), so over the 4-cube of the register qubits R_0..R_3 above the thread's
+// register-0 element z0,
+//   C(z0 + sum_{j in r} 2^R_j) = C(z0) + sum_{j in r} [C(z0 + 2^R_j) - C(z0)] + sum_{j<k in r} b_{R_j R_k},
+// and the last sum does not depend on z0.  cq[r] = sum_{k in r, k > j} b_{R_j R_k}, j the lowest
+// bit of r, so C at register r follows from C at r - 2^j in two additions.  Exact for integer
+// costs; for real ones within a few units in the last place of the stored values.  The loads read
+// 5/16 of the diagonal bytes the pass would otherwise read.
+using RegQ = const double __attribute__((address_space(4)));
+struct RegCost {
+    double v[16];  // entries are formed in ascending register order; only those still needed stay live
+    double k[4];   // C(z0 + 2^R_j) - C(z0)
+};
+
+template <typename DT, typename O>
+__device__ __forceinline__ void reg_cost_load(RegCost &c, uint64_t diag_a, uint64_t b, uint64_t rs, O vd)
+{
+    c.v[0] = (double)gld<DT>(diag_a + b * sizeof(DT), vd);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c.v[1 << j] = (double)gld<DT>(diag_a + (b + (rs << j)) * sizeof(DT), vd);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c.k[j] = c.v[1 << j] - c.v[0];
+}
+
+__device__ __forceinline__ double reg_cost(RegCost &c, RegQ *cq, int r)
+{
+    if ((r & (r - 1)) == 0) return c.v[r];
+    const int j = __builtin_ctz(r);
+    c.v[r] = (c.v[r - (1 << j)] + c.k[j]) + cq[r];
+    return c.v[r];
+}
+
 struct MixCoef {
     float m;      // t (form A) or u (form B), direction folded in
     int formB;
@@ -358,6 +390,7 @@ struct FastArgs {
     const PartDesc *part;  // partitioned phases (PART bodies only)
     const void *tables;    // packed per-QPU local tables
     const void *cross;     // cross-QPU diagonal, 2^n entries
+    const double *cq;      // 16 pair sums of the register qubits of the layout the diagonal is read in
 };
 
 // ---- partitioned phase (eq. (16)) --------------------------------------------------------------
@@ -521,8 +554,10 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         // registers at each use rather than hoisted out of the loop
         const uint64_t rs2 = opaque_u64(1ull << a.pos8), rs1 = opaque_u64(1ull << a.pos4);
         const uint64_t b2 = base + w2, b1 = base + w1;
-        auto cz2 = [&](int r) { return (double)gld<DT>(diag_a + (b2 + r * rs2) * sizeof(DT), vd2); };
-        auto cz1 = [&](int r) { return (double)gld<DT>(diag_a + (b1 + r * rs1) * sizeof(DT), vd1); };
+        RegQ *cq = (RegQ *)a.cq;
+        // cost values of the thread's registers in layout 2 / layout 1 (five loads each)
+        auto cz2 = [&](RegCost &rc) { reg_cost_load<DT>(rc, diag_a, b2, rs2, vd2); };
+        auto cz1 = [&](RegCost &rc) { reg_cost_load<DT>(rc, diag_a, b1, rs1, vd1); };
         auto ld2 = [&](uint64_t arr, int r) { return gld<float2>(arr + (b2 + r * rs2) * 8, vs2); };
         // stores take their own opaque copy of the stride: sharing the load addresses
         // would keep 16-32 scalar address pairs live across the whole tile
@@ -537,10 +572,12 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 for (int r = 0; r < kRegs; ++r) v[0][r] = make_float2((float)a.amp0, 0.0f);
                 apply_angles<NS, 1, false>(v, uf);
             } else {
+                RegCost rc;
+                cz2(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     float c, s;
-                    phase_rev(g2pi, cz2(r), c, s);
+                    phase_rev(g2pi, reg_cost(rc, cq, r), c, s);
                     v[0][r] = make_float2((float)a.amp0 * c, -(float)a.amp0 * s);
                     QQ_CHUNK_FENCE(r);
                 }
@@ -565,10 +602,12 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     part_angles<DT>(uf, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, rs1, vd1);
                     apply_angles<NS, 1, false>(v, uf);
                 } else {
+                    RegCost rc;
+                    cz1(rc);
 #pragma unroll
                     for (int r = 0; r < kRegs; ++r) {
                         float c, s;
-                        phase_rev(g2pi, cz1(r), c, s);
+                        phase_rev(g2pi, reg_cost(rc, cq, r), c, s);
                         rot_phase<float>(v[0][r], c, s);
                         QQ_CHUNK_FENCE(r);
                     }
@@ -579,10 +618,12 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 for (int r = 0; r < kRegs; ++r) st2f(psi_a, r, v[0][r], rss);
             } else {
                 double e = 0.0;
+                RegCost rc;
+                cz1(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
-                    e = fma((double)pz, cz1(r), e);
+                    e = fma((double)pz, reg_cost(rc, cq, r), e);
                     QQ_CHUNK_FENCE(r);
                 }
                 acc[0] += e;
@@ -598,9 +639,11 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             double gb = 0.0;
             mix_op<HIGH, FULL, 2, 2, 1, false, FB1>(lds, v, t, a.active, c1, gb);
             double e = 0.0;
+            RegCost rc;
+            cz1(rc);
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) {
-                const double cz = cz1(r);
+                const double cz = reg_cost(rc, cq, r);
                 const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
                 e = fma((double)pz, cz, e);
                 const float cf = (float)cz;
@@ -635,9 +678,11 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 }
             } else {
                 double gg = 0.0;
+                RegCost rc;
+                cz1(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
-                    const double cz = cz1(r);
+                    const double cz = reg_cost(rc, cq, r);
                     const float2 ps = v[0][r], la = v[1][r];
                     const float im = fmaf(la.x, ps.y, -la.y * ps.x);
                     gg = fma(cz, (double)im, gg);
