@@ -266,8 +266,9 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch measurement")
     ap.add_argument("--no-multi-qpu", action="store_true", help="skip the n = 32 multi-QPU measurement")
-    ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER]",
-                    help="pin this schedule (workgroups per state, set pairing, tile order) instead of autotuning")
+    ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER[:SETORDER]]",
+                    help="pin this schedule (workgroups per state, set pairing, tile order, set order) "
+                         "instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (reference kernel for the traffic counters)")
     args = ap.parse_args()
@@ -302,9 +303,9 @@ def main():
 
     if args.schedule:
         fields = [int(v) for v in args.schedule.split(":")]
-        G, pairing, order = (fields + [0, 0])[:3]
+        G, pairing, order, set_order = (fields + [0, 0, 0])[:4]
         N.qq_set_schedule(pb.handle, p, B, flags, {"workgroups_per_state": G, "set_pairing": pairing,
-                                                   "tile_order": order})
+                                                   "tile_order": order, "set_order": set_order})
     schedule = N.qq_get_schedule(pb.handle, p, B, flags)
     if not args.no_autotune and not args.schedule:
         progress("autotuning the schedule")

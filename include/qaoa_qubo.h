@@ -240,15 +240,24 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
  *                         n - 12 is a multiple of 8 with at least four runs
  *                         (0: run i with run m-1-i, 1: adjacent runs, 2: run i with
  *                         run i + m/2); otherwise only 0
- * Results do not depend on the schedule beyond the order of FP64 partial sums.
+ *   set_order             where the qubit-0..11 set sits in the order in which a
+ *                         layer visits the sets (the zig-zag reverses it every
+ *                         layer, so the first and last sets are where a pass
+ *                         applies the phase between two mixers): 0 first, 1 second
+ *                         (needs three or more sets); default 1 when n - 12 is a
+ *                         multiple of 8 of at least 16, else 0
+ * Results do not depend on workgroups_per_state and tile_order beyond the order of
+ * FP64 partial sums; set_pairing and set_order change the order of the complex64
+ * operations (differences at the complex64 rounding level).
  * qq_set_schedule pins one (NULL restores the default); qq_get_schedule reports
  * the one in force.  qq_workspace_size, qq_evaluate and qq_graph_create use it.
  *
  * qq_autotune times every candidate with HIP events on seeded parameter sets
  * (one warm-up, then the median of three runs, or one run when the warm-up
  * took over 200 ms): G of the default, half and double it, times
- * every pairing that applies, in the strided tile order; then the blocked tile
- * order at the best pairing for the best G, half and double it.  It pins the
+ * every pairing that applies, in the strided tile order and the default set
+ * order; then the blocked tile order at the best pairing for the best G, half and
+ * double it; then the other set order, where one applies, at the best of those.  It pins the
  * fastest and, if cache_path is not
  * NULL, appends it to that JSON-lines file; an entry already there for the same
  * device, n, p, batch, planning flags and diagonal width is used without timing.
@@ -267,6 +276,7 @@ typedef struct {
     int tried;        /* candidates timed by qq_autotune */
     int tile_order;   /* 0: workgroup g takes tiles g, g + G, ... (neighbouring tiles run together);
                          1: workgroup g takes a contiguous range of tiles (specialised kernels only) */
+    int set_order;    /* 0: the qubit-0..11 set first in a layer's visiting order; 1: second */
 } qq_schedule;
 
 qq_status qq_set_schedule(qq_problem *prob, int p, int batch, int flags, const qq_schedule *schedule);

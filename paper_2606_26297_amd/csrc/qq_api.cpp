@@ -136,7 +136,7 @@ struct qq_problem {
     PartDesc *d_part = nullptr;
     // schedules pinned by qq_set_schedule / qq_autotune, keyed by (p, batch, planning flags)
     struct Sched {
-        int p, batch, flags, G, pairing, blocked;
+        int p, batch, flags, G, pairing, blocked, set_order;
         double ms;
     };
     std::vector<Sched> sched;
@@ -177,6 +177,14 @@ constexpr int kPairings = 3;
 
 bool pairing_applies(int n) { return n > kTileBits && (n - kTileBits) % 8 == 0 && (n - kTileBits) / 4 >= 4; }
 
+// Visiting order of the sets in a layer: set_order 0 takes the qubit-0..11 set first, 1 second.
+// The zig-zag reverses the order every layer, so the first and last sets are where a pass mixes,
+// applies the next phase and mixes again; with the 12-qubit set in the middle those passes mix 8
+// qubits (less arithmetic per byte), measured faster on MI355X at n = 28.
+int num_sets(int n);
+bool set_order_applies(int n) { return num_sets(n) >= 3; }
+int default_set_order(int n) { return pairing_applies(n) ? 1 : 0; }
+
 std::vector<SetDesc> make_sets(int n, int pairing = 0)
 {
     std::vector<SetDesc> sets;
@@ -203,6 +211,8 @@ std::vector<SetDesc> make_sets(int n, int pairing = 0)
     }
     return sets;
 }
+
+int num_sets(int n) { return (int)make_sets(n, 0).size(); }
 
 struct PassPlan {
     int fkind = -1;  // FastPassKind of this pass (multi-pass plans)
@@ -274,16 +284,19 @@ Op op_acc(PassPlan &pp, uint8_t kind, int k, int out, uint8_t flags)
 // layer k on the set, applies phase k+1 and mixes layer k+1 on the same set.
 // A forward evaluation with s sets takes 1 + p(s-1) passes.  The adjoint
 // sweep runs the same zig-zag backwards over (psi, lambda).
-Plan make_plan(int n, int p, int mode, int pairing = 0)
+Plan make_plan(int n, int p, int mode, int pairing = 0, int set_order = 0)
 {
     Plan plan;
     plan.sets = make_sets(n, pairing);
     const int s = (int)plan.sets.size();
+    std::vector<int> vis(s);
+    for (int i = 0; i < s; ++i) vis[i] = i;
+    if (set_order == 1 && s >= 3) std::swap(vis[0], vis[1]);
     const bool grad = mode & PM_GRAD, energy = mode & (PM_ENERGY | PM_GRAD), store = mode & PM_STORE,
                part = mode & PM_PART;
     auto order = [&](int k) {
         std::vector<int> o(s);
-        for (int i = 0; i < s; ++i) o[i] = (k % 2 == 0) ? i : s - 1 - i;
+        for (int i = 0; i < s; ++i) o[i] = (k % 2 == 0) ? vis[i] : vis[s - 1 - i];
         return o;
     };
     auto act = [&](int set) { return plan.sets[set].active; };
@@ -455,7 +468,8 @@ const qq_problem::Sched *find_sched(const qq_problem *pb, int p, int batch, int 
 Plan plan_for(const qq_problem *pb, int p, int batch, int flags, bool store)
 {
     const auto *e = find_sched(pb, p, batch, flags);
-    return make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, store), e ? e->pairing : 0);
+    return make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, store), e ? e->pairing : 0,
+                     e ? e->set_order : default_set_order(pb->n));
 }
 
 Layout layout_for(const qq_problem *pb, int p, int batch, int flags, const Plan &plan)
@@ -860,7 +874,8 @@ qq_status time_median(hipStream_t stream, F run, double &ms)
     return QQ_OK;
 }
 
-void pin_sched(qq_problem *pb, int p, int batch, int flags, int G, int pairing, int blocked, double ms)
+void pin_sched(qq_problem *pb, int p, int batch, int flags, int G, int pairing, int blocked, int set_order,
+               double ms)
 {
     const int sf = sched_flags(flags);
     for (auto &e : pb->sched)
@@ -868,10 +883,11 @@ void pin_sched(qq_problem *pb, int p, int batch, int flags, int G, int pairing, 
             e.G = G;
             e.pairing = pairing;
             e.blocked = blocked;
+            e.set_order = set_order;
             e.ms = ms;
             return;
         }
-    pb->sched.push_back({p, batch, sf, G, pairing, blocked, ms});
+    pb->sched.push_back({p, batch, sf, G, pairing, blocked, set_order, ms});
 }
 
 uint64_t fnv1a(uint64_t h, int64_t v)
@@ -1846,7 +1862,9 @@ qq_status qq_set_schedule(qq_problem *pb, int p, int batch, int flags, const qq_
     if ((size_t)batch * (size_t)G > 0x7fffffffull) return fail(QQ_E_INVALID, "batch * workgroups_per_state too large");
     if (sch->tile_order != 0 && sch->tile_order != 1)
         return fail(QQ_E_INVALID, "tile_order = %d must be 0 (strided) or 1 (blocked)", sch->tile_order);
-    pin_sched(pb, p, batch, flags, G, sch->set_pairing, sch->tile_order, sch->ms);
+    if (sch->set_order < 0 || sch->set_order > 1 || (sch->set_order == 1 && !set_order_applies(pb->n)))
+        return fail(QQ_E_INVALID, "set_order = %d is not available at n = %d", sch->set_order, pb->n);
+    pin_sched(pb, p, batch, flags, G, sch->set_pairing, sch->tile_order, sch->set_order, sch->ms);
     return QQ_OK;
 }
 
@@ -1860,11 +1878,13 @@ qq_status qq_get_schedule(const qq_problem *pb, int p, int batch, int flags, qq_
         out->workgroups_per_state = e->G;
         out->set_pairing = e->pairing;
         out->tile_order = e->blocked;
+        out->set_order = e->set_order;
         out->ms = e->ms;
         out->pinned = 1;
     } else {
         out->workgroups_per_state = choose_G(pb->n, batch);
         out->set_pairing = 0;
+        out->set_order = default_set_order(pb->n);
     }
     return QQ_OK;
 }
@@ -1885,10 +1905,10 @@ qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *c
     const std::string key(keybuf);
     std::string line;
     if (cache_lookup(cache_path, key, line)) {
-        double G = 0, pr = 0, ms = 0, order = 0;
+        double G = 0, pr = 0, ms = 0, order = 0, so = 0;
         if (json_num(line, "G", G) && json_num(line, "pairing", pr) && json_num(line, "ms", ms) &&
-            json_num(line, "tile_order", order)) {
-            qq_schedule s{(int)G, (int)pr, ms, 1, 1, 0, (int)order};
+            json_num(line, "tile_order", order) && json_num(line, "set_order", so)) {
+            qq_schedule s{(int)G, (int)pr, ms, 1, 1, 0, (int)order, (int)so};
             if (qq_status st = qq_set_schedule(pb, p, batch, flags, &s); st == QQ_OK) {
                 *out = s;
                 return QQ_OK;
@@ -1897,7 +1917,8 @@ qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *c
         }
     }
     // stage 1: the heuristic G, half and double it, times every pairing where it applies (strided
-    // tile order); stage 2: the blocked tile order at the best pairing, for the best G, half and double
+    // tile order, default set order); stage 2: the blocked tile order at the best pairing, for the
+    // best G, half and double; stage 3: the other set order at the best of those
     const uint64_t T = tiles_per_state(pb->n);
     const int G0 = choose_G(pb->n, batch);
     auto g_candidates = [&](int Gc) {
@@ -1921,9 +1942,10 @@ qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *c
     QQ_HIP(hipMemcpy(dx.p, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice));
     const int eflags = flags | QQ_PARAMS_ON_DEVICE;
     double best = INFINITY;
-    int bestG = G0, bestP = 0, bestO = 0, tried = 0;
-    auto time_one = [&](int pr, int G, int order) -> qq_status {
-        const Plan plan = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false), pr);
+    const int so0 = default_set_order(pb->n);
+    int bestG = G0, bestP = 0, bestO = 0, bestS = so0, tried = 0;
+    auto time_one = [&](int pr, int G, int order, int so) -> qq_status {
+        const Plan plan = make_plan(pb->n, p, plan_mode(flags | QQ_ENERGY, false), pr, so);
         Layout L = make_layout(pb, p, batch, flags, plan, G);
         L.blocked = order;
         double ms = 0;
@@ -1938,24 +1960,27 @@ qq_status qq_autotune(qq_problem *pb, int p, int batch, int flags, const char *c
             bestG = G;
             bestP = pr;
             bestO = order;
+            bestS = so;
         }
         return QQ_OK;
     };
     for (int pr = 0; pr < npair; ++pr)
         for (int G : Gs)
-            if (qq_status st = time_one(pr, G, 0); st != QQ_OK) return st;
+            if (qq_status st = time_one(pr, G, 0, so0); st != QQ_OK) return st;
     const bool multi_pass = make_sets(pb->n, 0).size() > 1 && !(flags & QQ_C128) && pb->n <= kFastMaxN;
     if (multi_pass) {  // the tile order only applies to the specialised multi-pass kernels
         const int pr = bestP;
         for (int G : g_candidates(bestG))
-            if (qq_status st = time_one(pr, G, 1); st != QQ_OK) return st;
+            if (qq_status st = time_one(pr, G, 1, so0); st != QQ_OK) return st;
     }
-    pin_sched(pb, p, batch, flags, bestG, bestP, bestO, best);
+    if (set_order_applies(pb->n))
+        if (qq_status st = time_one(bestP, bestG, bestO, 1 - so0); st != QQ_OK) return st;
+    pin_sched(pb, p, batch, flags, bestG, bestP, bestO, bestS, best);
     char tail[200];
-    std::snprintf(tail, sizeof tail, "\"G\":%d,\"pairing\":%d,\"tile_order\":%d,\"ms\":%.4f}", bestG, bestP, bestO,
-                  best);
+    std::snprintf(tail, sizeof tail, "\"G\":%d,\"pairing\":%d,\"tile_order\":%d,\"set_order\":%d,\"ms\":%.4f}",
+                  bestG, bestP, bestO, bestS, best);
     if (qq_status st = cache_append(cache_path, key + tail); st != QQ_OK) return st;
-    *out = qq_schedule{bestG, bestP, best, 1, 0, tried, bestO};
+    *out = qq_schedule{bestG, bestP, best, 1, 0, tried, bestO, bestS};
     return QQ_OK;
 }
 

@@ -123,19 +123,14 @@ hipError_t launch_wide(const FastArgs &a, int diag_type, bool part, hipStream_t 
 template <int KIND>
 hipError_t launch_kind(const FastArgs &a, bool high, int diag_type, bool part, hipStream_t s)
 {
-    if constexpr (KIND == FK_FIRST) {
-        if (high) return hipErrorInvalidValue;  // the first pass always mixes qubits 0..11
-        return launch_k<KIND, false, true>(a, diag_type, part, s);
-    } else {
-        if (!high) return launch_k<KIND, false, true>(a, diag_type, part, s);  // the low set is always qubits 0..11
-        // largest layout-1 lane offset: (15 + 3 * 2^pos8) amplitudes of 8 bytes
-        const bool wide = ((15ull + (3ull << a.pos8)) * 8ull) >> 32 != 0;
-        if (a.active == 0x0ff0) {
-            if (wide) return hipErrorInvalidValue;  // full high sets stay below qubit 28 for n <= 34
-            return launch_k<KIND, true, true>(a, diag_type, part, s);
-        }
-        return wide ? launch_wide<KIND>(a, diag_type, part, s) : launch_k<KIND, true, false>(a, diag_type, part, s);
+    if (!high) return launch_k<KIND, false, true>(a, diag_type, part, s);  // the low set is always qubits 0..11
+    // largest layout-1 lane offset: (15 + 3 * 2^pos8) amplitudes of 8 bytes
+    const bool wide = ((15ull + (3ull << a.pos8)) * 8ull) >> 32 != 0;
+    if (a.active == 0x0ff0) {
+        if (wide) return hipErrorInvalidValue;  // full high sets stay below qubit 28 for n <= 34
+        return launch_k<KIND, true, true>(a, diag_type, part, s);
     }
+    return wide ? launch_wide<KIND>(a, diag_type, part, s) : launch_k<KIND, true, false>(a, diag_type, part, s);
 }
 
 }  // namespace

@@ -204,7 +204,7 @@ __device__ __forceinline__ void run_geom(int geom, const FastArgs &a, float2 *ld
 {
     if (geom == 0) {
         run_pass<KIND, false, true, DT>(a, lds, acc, t, b, g);
-    } else if constexpr (KIND != FK_FIRST) {
+    } else if constexpr (KIND != FK_FIRST) {  // the persistent plans take the qubit-0..11 set first
         if (geom == 1) run_pass<KIND, true, true, DT>(a, lds, acc, t, b, g);
         else run_pass<KIND, true, false, DT>(a, lds, acc, t, b, g);
     }

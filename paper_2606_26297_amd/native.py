@@ -69,7 +69,7 @@ class QQManyOptions(ctypes.Structure):
 class QQSchedule(ctypes.Structure):
     _fields_ = [("workgroups_per_state", ctypes.c_int), ("set_pairing", ctypes.c_int), ("ms", ctypes.c_double),
                 ("pinned", ctypes.c_int), ("from_cache", ctypes.c_int), ("tried", ctypes.c_int),
-                ("tile_order", ctypes.c_int)]
+                ("tile_order", ctypes.c_int), ("set_order", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p
@@ -379,16 +379,19 @@ def qq_graph_destroy(graph):
 
 def _sched_dict(s: QQSchedule):
     return {"workgroups_per_state": s.workgroups_per_state, "set_pairing": s.set_pairing, "ms": s.ms,
-            "pinned": s.pinned, "from_cache": s.from_cache, "tried": s.tried, "tile_order": s.tile_order}
+            "pinned": s.pinned, "from_cache": s.from_cache, "tried": s.tried, "tile_order": s.tile_order,
+            "set_order": s.set_order}
 
 
 def qq_set_schedule(handle, p, batch, flags, schedule):
-    """schedule: dict with workgroups_per_state and set_pairing, or None for the default."""
+    """schedule: dict with workgroups_per_state and optionally set_pairing, tile_order and
+    set_order (each 0 when absent), or None for the default."""
     if schedule is None:
         _check(lib().qq_set_schedule(handle, int(p), int(batch), int(flags), None))
         return
     s = QQSchedule(int(schedule["workgroups_per_state"]), int(schedule.get("set_pairing", 0)),
-                   float(schedule.get("ms", 0.0)), 0, 0, 0, int(schedule.get("tile_order", 0)))
+                   float(schedule.get("ms", 0.0)), 0, 0, 0, int(schedule.get("tile_order", 0)),
+                   int(schedule.get("set_order", 0)))
     _check(lib().qq_set_schedule(handle, int(p), int(batch), int(flags), ctypes.byref(s)))
 
 

@@ -132,6 +132,48 @@ def test_complex64_energy_and_gradient_vs_oracle(name, maker, p, batch):
     assert g_err(g, gref) <= 1e-5, (g, gref)
 
 
+SET_ORDER_CASES = [
+    ("n22_reg", lambda: W.regular_graph_qubo(22, 9), 3, 2),
+    ("n21_gauss", lambda: W.dense_gaussian_upper(21, 10), 2, 1),
+]
+
+
+@pytest.mark.parametrize("name,maker,p,batch", SET_ORDER_CASES, ids=[c[0] for c in SET_ORDER_CASES])
+def test_low_set_second_vs_oracle(name, maker, p, batch):
+    """Set order 1 (the qubit-0..11 set second in each layer's visiting order): the first pass and
+    the passes that apply a phase between two mixers run on high sets (one full, one partial at
+    these n).  complex64 and complex128 energies and gradients and the final complex64 state against
+    the oracle; the partitioned complex64 form against the monolithic one."""
+    inst = maker()
+    pb = make(inst)
+    d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+    x = W.random_params(p, batch, 3000 + inst.n)
+    GR = N.QQ_ENERGY | N.QQ_GRAD
+    for B, flags in ((batch, GR), (batch, N.QQ_ENERGY), (batch, GR | N.QQ_C128), (1, N.QQ_ENERGY)):
+        G = N.qq_get_schedule(pb.handle, p, B, flags)["workgroups_per_state"]
+        N.qq_set_schedule(pb.handle, p, B, flags, {"workgroups_per_state": G, "set_order": 1})
+        assert N.qq_get_schedule(pb.handle, p, B, flags)["set_order"] == 1
+    e, g = pb.evaluate(x, grad=True)
+    e_only = pb.evaluate(x)
+    e128, g128 = pb.evaluate(x, grad=True, c128=True)
+    ref = [O.gradient(d, xb) for xb in x]
+    eref = np.array([r[0] for r in ref])
+    gref = np.array([r[1] for r in ref])
+    sig = sigma_of(inst)
+    assert e_err(e, eref, sig) <= 1e-5 and e_err(e_only, eref, sig) <= 1e-5
+    assert g_err(g, gref) <= 1e-5
+    assert e_err(e128, eref, sig) <= 1e-11 and g_err(g128, gref) <= 1e-10
+    psi = pb.state(x[0])
+    assert np.linalg.norm(psi.astype(np.complex128) - O.qaoa_state(d, x[0])) <= 1e-5
+    caps = O.balanced_capacities(inst.n, 3)
+    pb.set_allocation(W.contiguous_allocation(inst.n, caps), 3, caps)
+    flags = GR | N.QQ_PARTITIONED
+    G = N.qq_get_schedule(pb.handle, p, batch, flags)["workgroups_per_state"]
+    N.qq_set_schedule(pb.handle, p, batch, flags, {"workgroups_per_state": G, "set_order": 1})
+    e1, g1 = pb.evaluate(x, grad=True, partitioned=True)
+    assert e_err(e1, eref, sig) <= 1e-5 and g_err(g1, gref) <= 1e-5
+
+
 C128_CASES = [
     ("n5", lambda: W.dense_gaussian_upper(5, 2), 3, 2),
     ("n12", lambda: W.workload1()[0], 2, 2),

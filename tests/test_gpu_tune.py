@@ -2,9 +2,10 @@
 
 * workgroups per state and the tile order only change which workgroup takes
   which tile: results agree to 1e-12 relative (order of the FP64 partial sums);
-* the set pairing changes which qubits share a pass, hence the complex64
-  rounding: every pairing is checked against the closed form of a separable
-  n = 28 problem (1e-5 relative);
+* the set pairing and the set order change which qubits share a pass and where
+  the phase is applied between two mixers, hence the complex64 rounding: every
+  (pairing, set order) is checked against the closed form of a separable n = 28
+  problem (1e-5 relative);
 * the autotuner pins a schedule that then evaluates correctly (oracle, 1e-5),
   writes its JSON-lines cache and reads it back without timing.
 """
@@ -63,7 +64,7 @@ def p1_qubit(ell, x):
     return abs(v[1]) ** 2
 
 
-def test_every_set_pairing_matches_the_separable_closed_form_at_n28():
+def test_every_set_pairing_and_order_matches_the_separable_closed_form_at_n28():
     n, p, B = 28, 2, 2
     inst = W.separable(n, 53, scale=0.5)
     pb = Problem(inst.H, inst.f, inst.c0)
@@ -71,10 +72,13 @@ def test_every_set_pairing_matches_the_separable_closed_form_at_n28():
     x = W.random_params(p, B, 54)
     eref = np.array([inst.c0 + sum(li * p1_qubit(li, xb) for li in ell) for xb in x])
     sig = pb.info.sigma_c
+    assert N.qq_get_schedule(pb.handle, p, B, N.QQ_ENERGY)["set_order"] == 1  # the default at n = 28
     for pairing in (0, 1, 2):
-        N.qq_set_schedule(pb.handle, p, B, N.QQ_ENERGY, {"workgroups_per_state": 256, "set_pairing": pairing})
-        e = pb.evaluate(x)
-        assert np.max(np.abs(e - eref) / np.maximum(np.abs(eref), sig)) <= 1e-5, pairing
+        for set_order in (0, 1):
+            N.qq_set_schedule(pb.handle, p, B, N.QQ_ENERGY,
+                              {"workgroups_per_state": 256, "set_pairing": pairing, "set_order": set_order})
+            e = pb.evaluate(x)
+            assert np.max(np.abs(e - eref) / np.maximum(np.abs(eref), sig)) <= 1e-5, (pairing, set_order)
 
 
 def test_invalid_schedules_are_rejected():
@@ -82,7 +86,8 @@ def test_invalid_schedules_are_rejected():
     pb = Problem(inst.H, inst.f, inst.c0)
     for bad in ({"workgroups_per_state": 3}, {"workgroups_per_state": 512}, {"workgroups_per_state": 0},
                 {"workgroups_per_state": 4, "set_pairing": 1}, {"workgroups_per_state": 4, "set_pairing": 3},
-                {"workgroups_per_state": 4, "tile_order": 2}):
+                {"workgroups_per_state": 4, "tile_order": 2}, {"workgroups_per_state": 4, "set_order": 2},
+                {"workgroups_per_state": 4, "set_order": 1}):  # n = 20 has two sets
         with pytest.raises(N.QQError) as ei:
             N.qq_set_schedule(pb.handle, 2, 2, GRAD, bad)
         assert ei.value.status == N.QQ_E_INVALID, bad
