@@ -205,6 +205,40 @@ def aux_kernels(dev, inst, x):
     return out
 
 
+def optimizer(dev, n=22, p_max=5, iterations=60, random_starts=16, perturbed_starts=15):
+    """Depth progression with multi-start search (qq_optimize) on a 3-regular instance of the timed
+    workload's generator: every depth runs all its starts as one batch of graph-captured Adam steps."""
+    import numpy as np
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd import workloads as W
+    from paper_2606_26297_amd.qaoa import Problem
+
+    inst = W.regular_graph_qubo(n, 303)
+    pb = Problem(inst.H, inst.f, inst.c0, device=0)
+    pts, off = W.optimizer_draws(p_max, random_starts, perturbed_starts, 304)
+    opts = {"p_max": p_max, "iterations": iterations, "random_starts": random_starts,
+            "perturbed_starts": perturbed_starts, "include_warm": 1, "adam": (0.05, 0.9, 0.999, 1e-8)}
+    N.qq_optimize(pb.handle, dict(opts, p_max=1, iterations=2), pts[:2 * random_starts])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = N.qq_optimize(pb.handle, opts, pts, off)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = pb.info
+    out = {"workload": f"3-regular graph QUBO, n = {n}, depths 1..{p_max}, {iterations} Adam steps per start, "
+                       f"{random_starts} random + 1 warm + {perturbed_starts} perturbed starts per depth "
+                       "(depth 1: random only), complex64 energy + adjoint gradient",
+           "seconds": round(dt, 3), "adam_steps": int(r["steps"]), "evaluations": int(r["evaluations"]),
+           "start_steps_per_s": round(r["steps"] / dt, 1), "best_depth": r["best_depth"],
+           "best_start": r["best_start"], "best_energy": r["best_energy"],
+           "depth_energy": [float(v) for v in r["depth_energy"]], "cmin": info.cmin, "cmax": info.cmax,
+           "approximation_ratio": (info.cmax - r["best_energy"]) / (info.cmax - info.cmin)}
+    pb.close()
+    return out
+
+
 def multi_qpu(dev):
     """The n = 32 multi-QPU workload: monolithic vs partitioned energy + gradient (device-resident)."""
     import numpy as np
@@ -266,6 +300,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch measurement")
     ap.add_argument("--no-multi-qpu", action="store_true", help="skip the n = 32 multi-QPU measurement")
+    ap.add_argument("--no-optimizer", action="store_true", help="skip the depth-progression search measurement")
     ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER[:SETORDER]]",
                     help="pin this schedule (workgroups per state, set pairing, tile order, set order) "
                          "instead of autotuning")
@@ -419,6 +454,10 @@ def main():
     if not args.no_multi_qpu:
         progress("multi-QPU n = 32")
         out["multi_qpu"] = multi_qpu(dev)
+        torch.cuda.empty_cache()
+    if not args.no_optimizer:
+        progress("depth-progression search")
+        out["optimizer"] = optimizer(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")

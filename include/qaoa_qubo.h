@@ -332,6 +332,65 @@ qq_status qq_graph_read(qq_graph *graph, double *energy, double *grad, double *h
 qq_status qq_graph_destroy(qq_graph *graph);
 
 /*
+ * Depth progression with multi-start search (Alg. 1 and the depth-progression /
+ * multi-start subsection), on the exact objective: for p = 1 .. p_max, every
+ * start runs `iterations` Adam steps of the exact energy with its adjoint
+ * gradient (qq_graph_* with all starts of the depth as one batch), the final
+ * parameter vector of every start is evaluated once more, the starts are ranked
+ * by that energy (ascending; ties to the lower start index) and the best is the
+ * depth's representative; the representatives are ranked the same way (ties to
+ * the lower depth) and the best is the result.
+ *
+ * Starts at depth p, in this order: the lifted representative of depth p - 1
+ * (p >= 2, if include_warm), perturbed_starts copies of it plus the given
+ * offsets (p >= 2), then random_starts given points.  Lifting (the paper does
+ * not fix it): linear interpolation of the gamma and beta sequences onto p + 1
+ * points, x'_i = ((i - 1) / p) x_{i-1} + ((p - i + 1) / p) x_i for i = 1 .. p + 1
+ * with x_0 = x_{p+1} = 0 (the INTERP rule of Zhou et al., Phys. Rev. X 10,
+ * 021067 (2020)), applied to gamma and beta separately.
+ *
+ * Random numbers are inputs:
+ *   random_points   host doubles: for p = 1 .. p_max in turn, random_starts
+ *                   interleaved [2p] vectors (random_starts * p_max (p_max + 1)
+ *                   doubles in all)
+ *   perturbations   host doubles: for p = 2 .. p_max in turn, perturbed_starts
+ *                   [2p] offsets (perturbed_starts * (p_max (p_max + 1) - 2)
+ *                   doubles); may be NULL when perturbed_starts = 0
+ * Outputs (host; each may be NULL except result):
+ *   result          best depth, its start index, its energy, counts
+ *   depth_params    [p_max][2 p_max] representative of every depth, zero padded
+ *   depth_energy    [p_max] their energies
+ *   start_energy    every start's final energy, depth-major: p = 1 has
+ *                   random_starts entries, every later depth
+ *                   include_warm + perturbed_starts + random_starts
+ * flags: 0, QQ_C128 and/or QQ_PARTITIONED (as for qq_evaluate).  Allocates its
+ * own device memory; synchronises `stream`.
+ * Errors: QQ_E_INVALID (options, missing inputs), and those of qq_graph_create
+ * and qq_evaluate.
+ */
+typedef struct {
+    int p_max;            /* depths 1 .. p_max, p_max <= QQ_MAX_P */
+    int iterations;       /* Adam steps of every start at every depth (>= 0) */
+    int random_starts;    /* random points per depth (>= 1) */
+    int perturbed_starts; /* perturbed warm starts per depth from depth 2 (>= 0) */
+    int include_warm;     /* 1: the lifted representative itself is a start from depth 2 */
+    int flags;            /* 0, QQ_C128, QQ_PARTITIONED */
+    double adam[4];       /* lr, beta1, beta2, eps (as qq_graph_create) */
+} qq_optimize_options;
+
+typedef struct {
+    int best_depth;        /* 1 .. p_max */
+    int best_start;        /* index of the chosen start at that depth */
+    double best_energy;
+    long long steps;       /* Adam steps taken, summed over starts */
+    long long evaluations; /* energy (+ gradient) evaluations, summed over starts */
+} qq_optimize_result;
+
+qq_status qq_optimize(qq_problem *prob, const qq_optimize_options *options, const double *random_points,
+                      const double *perturbations, void *stream, qq_optimize_result *result,
+                      double *depth_params, double *depth_energy, double *start_energy);
+
+/*
  * Measurement baseline: the plain complex128 form with one kernel per gate
  * (one phase kernel per layer, one RX kernel per qubit and layer, an energy
  * reduction, and the same adjoint equations unfused), one parameter set per

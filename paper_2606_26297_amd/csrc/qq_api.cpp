@@ -1081,6 +1081,15 @@ qq_status validate_many(int count, qq_problem *const *pbs, const int *p, const i
 
 }  // namespace
 
+namespace qq {
+qq_status set_error(qq_status st, const char *msg)
+{
+    g_err = msg;
+    return st;
+}
+int problem_device(const qq_problem *pb) { return pb->device; }
+}  // namespace qq
+
 extern "C" {
 
 const char *qq_last_error(void) { return g_err.c_str(); }

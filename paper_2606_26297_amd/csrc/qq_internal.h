@@ -217,6 +217,11 @@ struct AdamArgs {
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
 
+// Host helpers shared with the driver (qq_api.cpp): record the thread's error message; the
+// device a problem lives on.
+qq_status set_error(qq_status st, const char *msg);
+int problem_device(const qq_problem *pb);
+
 // Plain complex128 per-gate path (qq_plain.hip).
 struct PlainArgs {
     int n;

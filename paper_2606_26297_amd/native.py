@@ -72,6 +72,17 @@ class QQSchedule(ctypes.Structure):
                 ("tile_order", ctypes.c_int), ("set_order", ctypes.c_int)]
 
 
+class QQOptimizeOptions(ctypes.Structure):
+    _fields_ = [("p_max", ctypes.c_int), ("iterations", ctypes.c_int), ("random_starts", ctypes.c_int),
+                ("perturbed_starts", ctypes.c_int), ("include_warm", ctypes.c_int), ("flags", ctypes.c_int),
+                ("adam", ctypes.c_double * 4)]
+
+
+class QQOptimizeResult(ctypes.Structure):
+    _fields_ = [("best_depth", ctypes.c_int), ("best_start", ctypes.c_int), ("best_energy", ctypes.c_double),
+                ("steps", ctypes.c_longlong), ("evaluations", ctypes.c_longlong)]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -109,6 +120,8 @@ SIGNATURES = {
     "qq_get_schedule": ([_vp, _int, _int, _int, ctypes.POINTER(QQSchedule)], _int),
     "qq_autotune": ([_vp, _int, _int, _int, ctypes.c_char_p, _vp, ctypes.POINTER(QQSchedule)], _int),
     "qq_autotune_many": ([_int, _vp, _vp, _vp, _int, ctypes.c_char_p, _vp, ctypes.POINTER(QQManyOptions), _dp], _int),
+    "qq_optimize": ([_vp, ctypes.POINTER(QQOptimizeOptions), _dp, _dp, _vp, ctypes.POINTER(QQOptimizeResult), _dp, _dp,
+                     _dp], _int),
     "qq_profile_enable": ([_int], _int),
     "qq_profile_read": ([ctypes.c_void_p, _int, ctypes.POINTER(_int)], _int),
 }
@@ -375,6 +388,48 @@ def qq_graph_read(graph, batch, p, history=0, stream=None):
 
 def qq_graph_destroy(graph):
     _check(lib().qq_graph_destroy(graph))
+
+
+def optimize_starts(p_max, random_starts, perturbed_starts, include_warm):
+    """Starts per depth of qq_optimize (depth 1 has only the random ones)."""
+    return [random_starts + (0 if p == 1 else include_warm + perturbed_starts) for p in range(1, p_max + 1)]
+
+
+def qq_optimize(handle, options, random_points, perturbations=None, stream=None):
+    """Depth progression with multi-start search.  options: dict with p_max, iterations, random_starts,
+    perturbed_starts (0), include_warm (1), flags (0), adam ((0.01, 0.9, 0.999, 1e-8)).
+    random_points / perturbations: flat float64 arrays laid out as qq_optimize documents.
+    Returns a dict: best_depth, best_start, best_energy, steps, evaluations, depth_params
+    [p_max][2 p_max], depth_energy [p_max], start_energy (list of per-depth arrays)."""
+    pmax = int(options["p_max"])
+    R = int(options["random_starts"])
+    P = int(options.get("perturbed_starts", 0))
+    W = int(options.get("include_warm", 1))
+    o = QQOptimizeOptions(pmax, int(options["iterations"]), R, P, W, int(options.get("flags", 0)),
+                          (ctypes.c_double * 4)(*options.get("adam", (0.01, 0.9, 0.999, 1e-8))))
+    rp = np.ascontiguousarray(random_points, dtype=np.float64).ravel()
+    if rp.size != R * pmax * (pmax + 1):
+        raise ValueError(f"random_points holds {rp.size} values, expected {R * pmax * (pmax + 1)}")
+    pt = None
+    if P > 0 and pmax >= 2:
+        pt = np.ascontiguousarray(perturbations, dtype=np.float64).ravel()
+        if pt.size != P * (pmax * (pmax + 1) - 2):
+            raise ValueError(f"perturbations holds {pt.size} values, expected {P * (pmax * (pmax + 1) - 2)}")
+    starts = optimize_starts(pmax, R, P, W)
+    res = QQOptimizeResult()
+    dparams = np.zeros((pmax, 2 * pmax))
+    denergy = np.zeros(pmax)
+    senergy = np.zeros(sum(starts))
+    _check(lib().qq_optimize(handle, ctypes.byref(o), rp.ctypes.data_as(_dp),
+                             None if pt is None else pt.ctypes.data_as(_dp), _stream_ptr(stream), ctypes.byref(res),
+                             dparams.ctypes.data_as(_dp), denergy.ctypes.data_as(_dp), senergy.ctypes.data_as(_dp)))
+    per_depth, off = [], 0
+    for s in starts:
+        per_depth.append(senergy[off:off + s])
+        off += s
+    return {"best_depth": res.best_depth, "best_start": res.best_start, "best_energy": res.best_energy,
+            "steps": res.steps, "evaluations": res.evaluations, "depth_params": dparams, "depth_energy": denergy,
+            "start_energy": per_depth}
 
 
 def _sched_dict(s: QQSchedule):

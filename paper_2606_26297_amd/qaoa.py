@@ -34,6 +34,15 @@ class Problem:
     def info(self) -> N.QQInfo:
         return N.qq_problem_info(self.handle)
 
+    def optimize(self, p_max, iterations, random_points, perturbations=None, random_starts=1, perturbed_starts=0,
+                 include_warm=1, adam=(0.01, 0.9, 0.999, 1e-8), c128=False, partitioned=False, stream=None):
+        """Depth progression with multi-start search (qq_optimize); random inputs as laid out by
+        workloads.optimizer_draws."""
+        flags = (N.QQ_C128 if c128 else 0) | (N.QQ_PARTITIONED if partitioned else 0)
+        return N.qq_optimize(self.handle, {"p_max": p_max, "iterations": iterations, "random_starts": random_starts,
+                                           "perturbed_starts": perturbed_starts, "include_warm": include_warm,
+                                           "flags": flags, "adam": adam}, random_points, perturbations, stream)
+
     def coefficients(self):
         """(l, b, alpha, h, J) of eq. (4)-(5) and eq. (9)."""
         return N.qq_coefficients(self.handle, self.n)

@@ -46,6 +46,16 @@ def random_params(p: int, batch: int, seed: int, low: float = 0.0, high: float =
     return rng.uniform(low, high, size=(batch, 2 * p)).astype(np.float64)
 
 
+def optimizer_draws(p_max: int, random_starts: int, perturbed_starts: int, seed: int, scale: float = 0.1):
+    """Random inputs of the depth-progression / multi-start search, laid out depth by depth:
+    random points (for p = 1 .. p_max, random_starts vectors of 2p angles, U[0, pi]) and warm-start
+    offsets (for p = 2 .. p_max, perturbed_starts vectors of 2p values, N(0, scale^2))."""
+    rng = np.random.default_rng(seed)
+    pts = np.concatenate([rng.uniform(0.0, np.pi, size=random_starts * 2 * p) for p in range(1, p_max + 1)])
+    off = [rng.normal(0.0, scale, size=perturbed_starts * 2 * p) for p in range(2, p_max + 1)]
+    return pts.astype(np.float64), (np.concatenate(off) if off else np.zeros(0)).astype(np.float64)
+
+
 def dense_integer_symmetric(n: int, seed: int, lo: int = -10, hi: int = 10) -> Instance:
     """Integer entries drawn from {lo..hi} for i <= j, mirrored to a symmetric H; f = 0, c0 = 0."""
     rng = np.random.default_rng(seed)

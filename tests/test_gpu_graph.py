@@ -174,3 +174,34 @@ def test_problem_is_kept_while_a_graph_uses_it():
     pb.set_allocation(np.array([0] * 7 + [1] * 7), 2)
     pb.close()
     assert pb.handle is None
+
+
+def test_graph_step_with_the_low_set_second():
+    """A graph captured under a pinned schedule with set order 1 (n = 22, three sets): its first
+    step equals qq_evaluate under the same schedule bit for bit, and the energy is the oracle's."""
+    import torch
+
+    from oracle import oracle as O
+
+    inst = W.regular_graph_qubo(22, 91)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    p, B = 2, 2
+    GR = N.QQ_ENERGY | N.QQ_GRAD
+    G = N.qq_get_schedule(pb.handle, p, B, GR)["workgroups_per_state"]
+    N.qq_set_schedule(pb.handle, p, B, GR, {"workgroups_per_state": G, "set_order": 1})
+    x0 = W.random_params(p, B, 92)
+    xt = torch.tensor(x0, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    g = N.qq_graph_create(pb.handle, p, B, 0, None, xt, 2, stream)
+    try:
+        N.qq_graph_run(g, 1, stream)
+        torch.cuda.synchronize()
+        e, gr, _, steps = N.qq_graph_read(g, B, p, 2, stream)
+        assert steps == 1
+        e_ref, g_ref = pb.evaluate(x0, grad=True)
+        assert np.array_equal(e, e_ref) and np.array_equal(gr, g_ref)
+        d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+        er, _ = O.gradient(d, x0[0])
+        assert abs(e[0] - er) / max(abs(er), pb.info.sigma_c) <= 1e-5
+    finally:
+        N.qq_graph_destroy(g)
