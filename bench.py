@@ -239,6 +239,37 @@ def optimizer(dev, n=22, p_max=5, iterations=60, random_starts=16, perturbed_sta
     return out
 
 
+def sampling(dev, shots=1_000_000):
+    """Shots from the exact distribution of the timed workload's first parameter set (n = 28, p = 8)
+    and their metrics."""
+    import numpy as np
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd import workloads as W
+    from paper_2606_26297_amd.qaoa import Problem
+
+    inst, x = W.workload3(batch=1)
+    pb = Problem(inst.H, inst.f, inst.c0, device=0)
+    u = np.random.default_rng(305).uniform(0.0, 1.0, size=shots)
+    pb.sample(x[0], u[:1000])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    z = pb.sample(x[0], u)
+    t1 = time.perf_counter()
+    info = pb.info
+    st = pb.sample_stats(z, margin=0.5, k=10)
+    t2 = time.perf_counter()
+    out = {"workload": f"regular3_n28_p8 start 0, {shots} shots (state preparation included)",
+           "ms_sample": round(1000 * (t1 - t0), 2), "shots_per_s": round(shots / (t1 - t0), 1),
+           "ms_stats": round(1000 * (t2 - t1), 2),
+           "best_cost": st["best_cost"], "best_cost_mass": st["best_cost_mass"], "low_cost_mass_0.5": st["low_cost_mass"],
+           "mean_cost": st["mean_cost"], "distinct": st["distinct"], "exact_cost": info.cmin,
+           "exact_cost_mass": st["exact_cost_mass"], "elite_top3": [int(v) for v in st["elite_index"][:3]]}
+    pb.close()
+    return out
+
+
 def multi_qpu(dev):
     """The n = 32 multi-QPU workload: monolithic vs partitioned energy + gradient (device-resident)."""
     import numpy as np
@@ -301,6 +332,7 @@ def main():
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch measurement")
     ap.add_argument("--no-multi-qpu", action="store_true", help="skip the n = 32 multi-QPU measurement")
     ap.add_argument("--no-optimizer", action="store_true", help="skip the depth-progression search measurement")
+    ap.add_argument("--no-sampling", action="store_true", help="skip the shot-sampling measurement")
     ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER[:SETORDER]]",
                     help="pin this schedule (workgroups per state, set pairing, tile order, set order) "
                          "instead of autotuning")
@@ -458,6 +490,10 @@ def main():
     if not args.no_optimizer:
         progress("depth-progression search")
         out["optimizer"] = optimizer(dev)
+        torch.cuda.empty_cache()
+    if not args.no_sampling:
+        progress("shot sampling")
+        out["sampling"] = sampling(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")

@@ -332,6 +332,57 @@ qq_status qq_graph_read(qq_graph *graph, double *energy, double *grad, double *h
 qq_status qq_graph_destroy(qq_graph *graph);
 
 /*
+ * Shots from the exact output distribution (computational-basis measurement;
+ * the final shot-based evaluation and the metrics of the measurement decoding
+ * section, drawn from the exact state instead of a circuit simulator).
+ *
+ * qq_sample prepares the depth-p state of one parameter set (params as for
+ * qq_state) and draws `shots` basis indices: shot s takes the first index z
+ * whose cumulative probability sum_{y <= z} |psi(y)|^2 exceeds
+ * uniforms[s] * sum_y |psi(y)|^2 (inverse transform in basis order; sums in
+ * FP64; uniforms in [0, 1), drawn by the caller).  flags: QQ_C128,
+ * QQ_PARTITIONED; QQ_PARAMS_ON_DEVICE makes params and uniforms device
+ * pointers (device uniforms are not range-checked; values outside [0, 1) give
+ * the last index of nonzero probability); QQ_OUT_ON_DEVICE makes indices_out a
+ * device pointer.  Bit i-1 of an index is variable z_i.  Synchronises `stream`.
+ *
+ * qq_sample_stats summarises host indices (< 2^n) with the problem's stored
+ * costs: best sampled cost; the best sampled bitstring (among those of best
+ * cost the most frequent, ties to the lower index) and its frequency; the
+ * fraction of shots at the best cost; the sample mean of C (summed over
+ * distinct indices in index order); the low-cost mass (fraction of shots with
+ * C <= best + margin, margin >= 0 absolute); against the exact optimum of the
+ * problem (cmin, argmin_index): whether the best cost and bitstring match it,
+ * the fraction of shots at cost cmin and the frequency of argmin_index; and the
+ * k most frequent bitstrings (ties to the lower index) with their counts and
+ * costs (elite_cost may be NULL; entries beyond the distinct count are zero).
+ * Errors: QQ_E_INVALID, QQ_E_NOMEM, QQ_E_DEVICE and those of qq_state.
+ */
+typedef struct {
+    int64_t shots;
+    int64_t distinct;              /* distinct sampled indices */
+    uint64_t best_index;
+    double best_cost;
+    double best_frequency;         /* count of best_index / shots */
+    double best_cost_mass;         /* shots at best_cost / shots */
+    double mean_cost;
+    double low_cost_mass;          /* shots with C <= best_cost + margin / shots */
+    double exact_cost;             /* cmin of the problem */
+    uint64_t exact_index;          /* argmin_index of the problem */
+    int matches_exact_cost;
+    int matches_exact_index;
+    double exact_cost_mass;        /* shots at cost cmin / shots */
+    double exact_index_frequency;  /* count of argmin_index / shots */
+    int elite;                     /* entries filled in the elite arrays: min(k, distinct) */
+} qq_sample_stats_t;
+
+qq_status qq_sample(qq_problem *prob, int p, const double *params, int flags, int64_t shots, const double *uniforms,
+                    void *stream, uint64_t *indices_out);
+qq_status qq_sample_stats(qq_problem *prob, int64_t shots, const uint64_t *indices, double margin, int k,
+                          void *stream, qq_sample_stats_t *out, uint64_t *elite_index, int64_t *elite_count,
+                          double *elite_cost);
+
+/*
  * Depth progression with multi-start search (Alg. 1 and the depth-progression /
  * multi-start subsection), on the exact objective: for p = 1 .. p_max, every
  * start runs `iterations` Adam steps of the exact energy with its adjoint

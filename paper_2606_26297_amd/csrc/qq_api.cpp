@@ -1510,6 +1510,136 @@ qq_status qq_state(qq_problem *pb, int p, const double *params, int flags, void 
     return QQ_OK;
 }
 
+qq_status qq_sample(qq_problem *pb, int p, const double *params, int flags, int64_t shots, const double *uniforms,
+                    void *stream_, uint64_t *indices_out)
+{
+    g_err.clear();
+    if (!uniforms || !indices_out) return fail(QQ_E_INVALID, "uniforms / indices_out is NULL");
+    if (shots < 1) return fail(QQ_E_INVALID, "shots = %lld must be >= 1", (long long)shots);
+    if (flags & ~(QQ_C128 | QQ_PARTITIONED | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE))
+        return fail(QQ_E_INVALID, "flags 0x%x: only QQ_C128, QQ_PARTITIONED and the *_ON_DEVICE flags apply", flags);
+    const bool dev_in = flags & QQ_PARAMS_ON_DEVICE, dev_out = flags & QQ_OUT_ON_DEVICE;
+    if (!dev_in)
+        for (int64_t i = 0; i < shots; ++i)
+            if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0))
+                return fail(QQ_E_INVALID, "uniforms[%lld] = %g is not in [0, 1)", (long long)i, uniforms[i]);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    DevBuf own;
+    Layout L;
+    if (qq_status st = state_into(pb, p, params, flags, stream, own, L); st != QQ_OK) return st;
+    const void *psi = static_cast<char *>(own.p) + L.psi;
+    const bool c128 = flags & QQ_C128;
+    const uint64_t nblk = std::max<uint64_t>(1, pb->dim >> kTileBits);
+    const size_t o_start = align_up(nblk * sizeof(double)), o_u = o_start + align_up((nblk + 1) * sizeof(double)),
+                 o_out = o_u + (dev_in ? 0 : align_up((size_t)shots * sizeof(double))),
+                 total = o_out + (dev_out ? 0 : align_up((size_t)shots * sizeof(uint64_t)));
+    DevBuf buf;
+    if (hipMalloc(&buf.p, total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) for the shots failed", total);
+    char *b = static_cast<char *>(buf.p);
+    double *d_mass = reinterpret_cast<double *>(b), *d_start = reinterpret_cast<double *>(b + o_start);
+    const double *d_u = dev_in ? uniforms : reinterpret_cast<const double *>(b + o_u);
+    uint64_t *d_out = dev_out ? indices_out : reinterpret_cast<uint64_t *>(b + o_out);
+    if (!dev_in)
+        QQ_HIP(hipMemcpyAsync(b + o_u, uniforms, (size_t)shots * sizeof(double), hipMemcpyHostToDevice, stream));
+    QQ_HIP(launch_block_mass(psi, c128, pb->dim, nblk, d_mass, stream));
+    // prefix over the block masses in index order (host, sequential FP64)
+    std::vector<double> h(nblk), start(nblk + 1);
+    QQ_HIP(hipMemcpyAsync(h.data(), d_mass, nblk * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    start[0] = 0.0;
+    for (uint64_t i = 0; i < nblk; ++i) start[i + 1] = start[i] + h[i];
+    QQ_HIP(hipMemcpyAsync(d_start, start.data(), (nblk + 1) * sizeof(double), hipMemcpyHostToDevice, stream));
+    QQ_HIP(launch_shots(psi, c128, pb->dim, nblk, d_start, d_u, shots, d_out, stream));
+    if (!dev_out)
+        QQ_HIP(hipMemcpyAsync(indices_out, d_out, (size_t)shots * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    return QQ_OK;
+}
+
+qq_status qq_sample_stats(qq_problem *pb, int64_t shots, const uint64_t *indices, double margin, int k, void *stream_,
+                          qq_sample_stats_t *out, uint64_t *elite_index, int64_t *elite_count, double *elite_cost)
+{
+    g_err.clear();
+    if (!pb || !indices || !out) return fail(QQ_E_INVALID, "problem / indices / out is NULL");
+    if (shots < 1) return fail(QQ_E_INVALID, "shots = %lld must be >= 1", (long long)shots);
+    if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(QQ_E_INVALID, "margin must be finite and >= 0");
+    if (k < 0) return fail(QQ_E_INVALID, "k = %d must be >= 0", k);
+    if (k > 0 && (!elite_index || !elite_count)) return fail(QQ_E_INVALID, "elite_index / elite_count is NULL");
+    for (int64_t i = 0; i < shots; ++i)
+        if (indices[i] >= pb->dim) return fail(QQ_E_INVALID, "indices[%lld] is not below 2^n", (long long)i);
+    // distinct sampled bitstrings and their counts, in index order
+    std::vector<uint64_t> sorted(indices, indices + shots);
+    std::sort(sorted.begin(), sorted.end());
+    std::vector<uint64_t> uniq;
+    std::vector<int64_t> cnt;
+    for (int64_t i = 0; i < shots; ++i) {
+        if (i == 0 || sorted[i] != sorted[i - 1]) {
+            uniq.push_back(sorted[i]);
+            cnt.push_back(0);
+        }
+        ++cnt.back();
+    }
+    const int64_t m = (int64_t)uniq.size();
+    // their costs from the stored diagonal
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(pb->device));
+    DevBuf buf;
+    if (hipMalloc(&buf.p, (size_t)m * 16) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc failed");
+    uint64_t *d_idx = static_cast<uint64_t *>(buf.p);
+    double *d_cost = reinterpret_cast<double *>(d_idx + m);
+    std::vector<double> cost(m);
+    QQ_HIP(hipMemcpyAsync(d_idx, uniq.data(), (size_t)m * 8, hipMemcpyHostToDevice, stream));
+    QQ_HIP(launch_gather_cost(pb->d_diag, pb->diag_type, d_idx, m, d_cost, stream));
+    QQ_HIP(hipMemcpyAsync(cost.data(), d_cost, (size_t)m * 8, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+
+    std::memset(out, 0, sizeof *out);
+    const double S = (double)shots;
+    double best = INFINITY, mean = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        best = std::min(best, cost[i]);
+        mean += (double)cnt[i] * cost[i];
+    }
+    int64_t bi = -1, at_best = 0, low = 0, at_exact = 0, exact_idx = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (cost[i] == best) {
+            at_best += cnt[i];
+            if (bi < 0 || cnt[i] > cnt[bi]) bi = i;  // most frequent, then lowest index
+        }
+        if (cost[i] <= best + margin) low += cnt[i];
+        if (cost[i] == pb->cmin) at_exact += cnt[i];
+        if (uniq[i] == pb->argmin) exact_idx = cnt[i];
+    }
+    out->shots = shots;
+    out->distinct = m;
+    out->best_index = uniq[bi];
+    out->best_cost = best;
+    out->best_frequency = (double)cnt[bi] / S;
+    out->best_cost_mass = (double)at_best / S;
+    out->mean_cost = mean / S;
+    out->low_cost_mass = (double)low / S;
+    out->exact_cost = pb->cmin;
+    out->exact_index = pb->argmin;
+    out->matches_exact_cost = best == pb->cmin ? 1 : 0;
+    out->matches_exact_index = uniq[bi] == pb->argmin ? 1 : 0;
+    out->exact_cost_mass = (double)at_exact / S;
+    out->exact_index_frequency = (double)exact_idx / S;
+    // elite: the k most frequent, ties to the lower index
+    std::vector<int64_t> order(m);
+    for (int64_t i = 0; i < m; ++i) order[i] = i;
+    const int64_t kk = std::min<int64_t>(k, m);
+    std::partial_sort(order.begin(), order.begin() + kk, order.end(),
+                      [&](int64_t a, int64_t b) { return cnt[a] > cnt[b] || (cnt[a] == cnt[b] && uniq[a] < uniq[b]); });
+    for (int j = 0; j < k; ++j) {
+        const bool have = j < kk;
+        elite_index[j] = have ? uniq[order[j]] : 0;
+        elite_count[j] = have ? cnt[order[j]] : 0;
+        if (elite_cost) elite_cost[j] = have ? cost[order[j]] : 0.0;
+    }
+    out->elite = (int)kk;
+    return QQ_OK;
+}
+
 qq_status qq_probabilities(qq_problem *pb, int p, const double *params, int flags, double *prob_out, void *stream_)
 {
     g_err.clear();

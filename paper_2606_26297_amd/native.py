@@ -72,6 +72,16 @@ class QQSchedule(ctypes.Structure):
                 ("tile_order", ctypes.c_int), ("set_order", ctypes.c_int)]
 
 
+class QQSampleStats(ctypes.Structure):
+    _fields_ = [("shots", ctypes.c_int64), ("distinct", ctypes.c_int64), ("best_index", ctypes.c_uint64),
+                ("best_cost", ctypes.c_double), ("best_frequency", ctypes.c_double),
+                ("best_cost_mass", ctypes.c_double), ("mean_cost", ctypes.c_double),
+                ("low_cost_mass", ctypes.c_double), ("exact_cost", ctypes.c_double), ("exact_index", ctypes.c_uint64),
+                ("matches_exact_cost", ctypes.c_int), ("matches_exact_index", ctypes.c_int),
+                ("exact_cost_mass", ctypes.c_double), ("exact_index_frequency", ctypes.c_double),
+                ("elite", ctypes.c_int)]
+
+
 class QQOptimizeOptions(ctypes.Structure):
     _fields_ = [("p_max", ctypes.c_int), ("iterations", ctypes.c_int), ("random_starts", ctypes.c_int),
                 ("perturbed_starts", ctypes.c_int), ("include_warm", ctypes.c_int), ("flags", ctypes.c_int),
@@ -122,6 +132,9 @@ SIGNATURES = {
     "qq_autotune_many": ([_int, _vp, _vp, _vp, _int, ctypes.c_char_p, _vp, ctypes.POINTER(QQManyOptions), _dp], _int),
     "qq_optimize": ([_vp, ctypes.POINTER(QQOptimizeOptions), _dp, _dp, _vp, ctypes.POINTER(QQOptimizeResult), _dp, _dp,
                      _dp], _int),
+    "qq_sample": ([_vp, _int, _vp, _int, ctypes.c_int64, _vp, _vp, _vp], _int),
+    "qq_sample_stats": ([_vp, ctypes.c_int64, _u64p, ctypes.c_double, _int, _vp, ctypes.POINTER(QQSampleStats), _u64p,
+                         _i64p, _dp], _int),
     "qq_profile_enable": ([_int], _int),
     "qq_profile_read": ([ctypes.c_void_p, _int, ctypes.POINTER(_int)], _int),
 }
@@ -388,6 +401,41 @@ def qq_graph_read(graph, batch, p, history=0, stream=None):
 
 def qq_graph_destroy(graph):
     _check(lib().qq_graph_destroy(graph))
+
+
+def qq_sample(handle, p, params, uniforms, flags=0, stream=None, out=None):
+    """Shots from the exact distribution: basis indices (uint64) for the given uniforms in [0, 1).
+    Host numpy inputs, or torch device tensors with QQ_PARAMS_ON_DEVICE (params and uniforms) and
+    QQ_OUT_ON_DEVICE (out, a device uint64/int64 tensor of the shot count)."""
+    if flags & QQ_PARAMS_ON_DEVICE:
+        pp, up, shots = _dev_ptr(params), _dev_ptr(uniforms), int(uniforms.numel())
+    else:
+        params = np.ascontiguousarray(params, dtype=np.float64).ravel()
+        uniforms = np.ascontiguousarray(uniforms, dtype=np.float64).ravel()
+        pp, up, shots = params.ctypes.data_as(_vp), uniforms.ctypes.data_as(_vp), int(uniforms.size)
+    if flags & QQ_OUT_ON_DEVICE:
+        op = _dev_ptr(out)
+    else:
+        out = np.empty(shots, dtype=np.uint64)
+        op = out.ctypes.data_as(_vp)
+    _check(lib().qq_sample(handle, int(p), pp, int(flags), shots, up, _stream_ptr(stream), op))
+    return out
+
+
+def qq_sample_stats(handle, indices, margin=0.0, k=10, stream=None):
+    """Summary of sampled indices (host): a dict of the qq_sample_stats_t fields plus elite_index,
+    elite_count and elite_cost (the k most frequent, ties to the lower index)."""
+    idx = np.ascontiguousarray(indices, dtype=np.uint64).ravel()
+    st = QQSampleStats()
+    ei = np.zeros(max(k, 1), dtype=np.uint64)
+    ec = np.zeros(max(k, 1), dtype=np.int64)
+    eco = np.zeros(max(k, 1), dtype=np.float64)
+    _check(lib().qq_sample_stats(handle, int(idx.size), idx.ctypes.data_as(_u64p), float(margin), int(k),
+                                 _stream_ptr(stream), ctypes.byref(st), ei.ctypes.data_as(_u64p),
+                                 ec.ctypes.data_as(_i64p), eco.ctypes.data_as(_dp)))
+    d = {name: getattr(st, name) for name, _ in QQSampleStats._fields_}
+    d["elite_index"], d["elite_count"], d["elite_cost"] = ei[:st.elite], ec[:st.elite], eco[:st.elite]
+    return d
 
 
 def optimize_starts(p_max, random_starts, perturbed_starts, include_warm):

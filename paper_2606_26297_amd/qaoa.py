@@ -10,6 +10,19 @@ import numpy as np
 from . import native as N
 
 
+def rank_key(stats, use_reference=False):
+    """Sort key (smaller is better) of a sampled candidate, following the ranking of the
+    depth-progression / multi-start subsection: with a classical reference, agreement with the exact
+    optimum cost, then with its bitstring, then the shot fractions at that cost and at that
+    bitstring; then (and alone without a reference) the best sampled cost, the fraction of shots at
+    it, the frequency of the best sampled bitstring and the sample mean cost."""
+    base = (stats["best_cost"], -stats["best_cost_mass"], -stats["best_frequency"], stats["mean_cost"])
+    if not use_reference:
+        return base
+    return (-stats["matches_exact_cost"], -stats["matches_exact_index"], -stats["exact_cost_mass"],
+            -stats["exact_index_frequency"]) + base
+
+
 class Problem:
     """A QUBO in the dense input form F(z) = c0 + f^T z + z^T H z (eq. (2)), resident on one GPU."""
 
@@ -42,6 +55,17 @@ class Problem:
         return N.qq_optimize(self.handle, {"p_max": p_max, "iterations": iterations, "random_starts": random_starts,
                                            "perturbed_starts": perturbed_starts, "include_warm": include_warm,
                                            "flags": flags, "adam": adam}, random_points, perturbations, stream)
+
+    def sample(self, x, uniforms, c128=False, partitioned=False):
+        """Basis indices of shots from the exact distribution of the state at x (one parameter set),
+        one per uniform in [0, 1)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+        flags = (N.QQ_C128 if c128 else 0) | (N.QQ_PARTITIONED if partitioned else 0)
+        return N.qq_sample(self.handle, x.shape[0] // 2, x, uniforms, flags)
+
+    def sample_stats(self, indices, margin=0.0, k=10):
+        """Sampled-solution metrics of host indices (qq_sample_stats)."""
+        return N.qq_sample_stats(self.handle, indices, margin, k)
 
     def coefficients(self):
         """(l, b, alpha, h, J) of eq. (4)-(5) and eq. (9)."""
