@@ -308,6 +308,11 @@ def multi_qpu(dev):
     sig = pb.info.sigma_c
     (e0, g0), (e1, g1) = res["monolithic"], res["partitioned"]
     out["partitioned_overhead"] = round(out["partitioned"]["ms"] / out["monolithic"]["ms"], 3)
+    t0 = time.perf_counter()
+    _, cross, remote, best = N.qq_allocation_candidates(inst.H, len(caps), p, capacities=caps)
+    out["allocation_candidates"] = {"graph_aware_cross": int(cross[0]), "contiguous_cross": int(cross[1]),
+                                    "best": ["graph_aware", "contiguous"][best],
+                                    "ms": round(1000 * (time.perf_counter() - t0), 3)}
     out["partitioned_vs_monolithic"] = {
         "energy_rel": float(np.max(np.abs(e1 - e0) / np.maximum(np.abs(e0), sig))),
         "grad_rel": float(np.max(np.abs(g1 - g0)) / np.max(np.abs(g0)))}

@@ -332,6 +332,45 @@ qq_status qq_graph_read(qq_graph *graph, double *energy, double *grad, double *h
 qq_status qq_graph_destroy(qq_graph *graph);
 
 /*
+ * Variable-to-QPU allocation (multi-QPU variable allocation section, Fig. 1).
+ * Host-only functions of the dense input form (H as for qq_problem_create, n x n
+ * row-major host array); they need no device and feed qq_set_allocation.
+ *   qq_balanced_capacities  c_m = floor(n / M) + [m < n mod M] (the paper's
+ *                           "as evenly as possible"; 1 <= M <= n)
+ *   qq_allocation           one strategy: QQ_ALLOC_CONTIGUOUS fills QPU 0, 1, ...
+ *                           with variables in order up to their capacities;
+ *                           QQ_ALLOC_GRAPH is a greedy on the weighted coupling
+ *                           graph w_ij = |H_ij + H_ji| (the paper names the step
+ *                           but not its rule): QPUs are filled in turn, each
+ *                           from the unassigned variable of largest strength
+ *                           s(v) = sum_u w_uv, then by largest gain
+ *                           2 w(v, QPU) - s(v), ties to the lower index.  Every
+ *                           QPU keeps room for one variable per later QPU.
+ *                           capacities: M host ints >= 1 summing to >= n, or
+ *                           NULL for the balanced ones.  qpu_out: n ints (0-based
+ *                           QPU of each variable); cross_out (may be NULL): the
+ *                           number of nonzero couplings across QPUs (eq. (16)).
+ *   qq_allocation_candidates  the graph-aware, the contiguous and (if manual is
+ *                           not NULL) the given allocation, in that order, with
+ *                           their cross counts and remote-CNOT estimates
+ *                           2 x cross x p (remote_out may be NULL); best = the
+ *                           candidate with the fewest cross terms, ties to the
+ *                           earlier one in that order (the paper's fixed type
+ *                           priority is not given; this order is the reading).
+ *                           qpu_out: 3 x n ints, count = 2 or 3.
+ * Errors: QQ_E_INVALID.
+ */
+#define QQ_ALLOC_CONTIGUOUS 0
+#define QQ_ALLOC_GRAPH 1
+
+qq_status qq_balanced_capacities(int n, int num_qpus, int *capacities_out);
+qq_status qq_allocation(int n, const double *H, int num_qpus, const int *capacities, int strategy, int32_t *qpu_out,
+                        int64_t *cross_out);
+qq_status qq_allocation_candidates(int n, const double *H, int num_qpus, const int *capacities,
+                                   const int32_t *manual, int p, int32_t *qpu_out, int64_t *cross_out,
+                                   int64_t *remote_out, int *count, int *best);
+
+/*
  * Shots from the exact output distribution (computational-basis measurement;
  * the final shot-based evaluation and the metrics of the measurement decoding
  * section, drawn from the exact state instead of a circuit simulator).

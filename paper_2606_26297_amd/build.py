@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["qq_kernels.hip", "qq_fast.hip", "qq_many.hip", "qq_optim.hip", "qq_plain.hip", "qq_sample.hip"]
-CPP_SOURCES = ["qq_api.cpp", "qq_driver.cpp"]
+CPP_SOURCES = ["qq_api.cpp", "qq_driver.cpp", "qq_alloc.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 # Device code: gfx950 only; packed FP32 instructions disabled.

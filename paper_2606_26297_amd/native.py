@@ -135,6 +135,10 @@ SIGNATURES = {
     "qq_sample": ([_vp, _int, _vp, _int, ctypes.c_int64, _vp, _vp, _vp], _int),
     "qq_sample_stats": ([_vp, ctypes.c_int64, _u64p, ctypes.c_double, _int, _vp, ctypes.POINTER(QQSampleStats), _u64p,
                          _i64p, _dp], _int),
+    "qq_balanced_capacities": ([_int, _int, _vp], _int),
+    "qq_allocation": ([_int, _dp, _int, _vp, _int, _i32p, _i64p], _int),
+    "qq_allocation_candidates": ([_int, _dp, _int, _vp, _i32p, _int, _i32p, _i64p, _i64p, ctypes.POINTER(_int),
+                                  ctypes.POINTER(_int)], _int),
     "qq_profile_enable": ([_int], _int),
     "qq_profile_read": ([ctypes.c_void_p, _int, ctypes.POINTER(_int)], _int),
 }
@@ -436,6 +440,52 @@ def qq_sample_stats(handle, indices, margin=0.0, k=10, stream=None):
     d = {name: getattr(st, name) for name, _ in QQSampleStats._fields_}
     d["elite_index"], d["elite_count"], d["elite_cost"] = ei[:st.elite], ec[:st.elite], eco[:st.elite]
     return d
+
+
+QQ_ALLOC_CONTIGUOUS = 0
+QQ_ALLOC_GRAPH = 1
+
+
+def qq_balanced_capacities(n, num_qpus):
+    out = np.zeros(num_qpus, dtype=np.int32)
+    _check(lib().qq_balanced_capacities(int(n), int(num_qpus), out.ctypes.data_as(_vp)))
+    return out
+
+
+def _caps(capacities):
+    return None if capacities is None else np.ascontiguousarray(capacities, dtype=np.int32)
+
+
+def qq_allocation(H, num_qpus, capacities=None, strategy=QQ_ALLOC_GRAPH):
+    """(qpu of each variable, cross count) of one allocation strategy (host only)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    n = H.shape[0]
+    caps = _caps(capacities)
+    q = np.zeros(n, dtype=np.int32)
+    x = ctypes.c_int64(0)
+    _check(lib().qq_allocation(n, H.ctypes.data_as(_dp), int(num_qpus), None if caps is None else caps.ctypes.data_as(_vp),
+                               int(strategy), q.ctypes.data_as(_i32p), ctypes.byref(x)))
+    return q, x.value
+
+
+def qq_allocation_candidates(H, num_qpus, p, capacities=None, manual=None):
+    """Candidates [graph-aware, contiguous, (manual)]: (qpu arrays, cross counts, remote-CNOT estimates,
+    index of the best)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    n = H.shape[0]
+    caps = _caps(capacities)
+    man = None if manual is None else np.ascontiguousarray(manual, dtype=np.int32)
+    q = np.zeros((3, n), dtype=np.int32)
+    cross = np.zeros(3, dtype=np.int64)
+    remote = np.zeros(3, dtype=np.int64)
+    count, best = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().qq_allocation_candidates(n, H.ctypes.data_as(_dp), int(num_qpus),
+                                          None if caps is None else caps.ctypes.data_as(_vp),
+                                          None if man is None else man.ctypes.data_as(_i32p), int(p),
+                                          q.ctypes.data_as(_i32p), cross.ctypes.data_as(_i64p),
+                                          remote.ctypes.data_as(_i64p), ctypes.byref(count), ctypes.byref(best)))
+    k = count.value
+    return q[:k], cross[:k], remote[:k], best.value
 
 
 def optimize_starts(p_max, random_starts, perturbed_starts, include_warm):
