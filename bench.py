@@ -270,6 +270,35 @@ def sampling(dev, shots=1_000_000):
     return out
 
 
+def telegate(dev):
+    """One gate-level trajectory of the distributed circuit with explicit TeleGate remote CNOTs: the
+    12-variable integer case, 3 QPUs of 4 (contiguous), p = 2, against the exact state."""
+    import numpy as np
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd import workloads as W
+    from paper_2606_26297_amd.qaoa import Problem
+
+    inst, _ = W.workload1()
+    n = inst.H.shape[0]
+    pb = Problem(inst.H, inst.f, inst.c0, device=0)
+    cross, _ = pb.set_allocation(W.contiguous_allocation(n, [4, 4, 4]), 3, [4, 4, 4])
+    x = W.random_params(2, 1, 306)[0]
+    u = np.random.default_rng(307).uniform(size=4 * cross * 2)
+    N.qq_telegate_state(pb.handle, n, x, u)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi, outcomes, remote = N.qq_telegate_state(pb.handle, n, x, u)
+    dt = time.perf_counter() - t0
+    exact = pb.state(x, c128=True)
+    out = {"workload": f"12-variable integer QUBO, 3 QPUs x 4 (contiguous), p = 2, {cross} cross terms",
+           "remote_cnots": int(remote), "measurements": int(outcomes.size), "ms": round(1000 * dt, 2),
+           "max_abs_diff_vs_exact_state": float(np.max(np.abs(psi - exact)))}
+    pb.close()
+    return out
+
+
 def multi_qpu(dev):
     """The n = 32 multi-QPU workload: monolithic vs partitioned energy + gradient (device-resident)."""
     import numpy as np
@@ -338,6 +367,7 @@ def main():
     ap.add_argument("--no-multi-qpu", action="store_true", help="skip the n = 32 multi-QPU measurement")
     ap.add_argument("--no-optimizer", action="store_true", help="skip the depth-progression search measurement")
     ap.add_argument("--no-sampling", action="store_true", help="skip the shot-sampling measurement")
+    ap.add_argument("--no-telegate", action="store_true", help="skip the TeleGate trajectory measurement")
     ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER[:SETORDER]]",
                     help="pin this schedule (workgroups per state, set pairing, tile order, set order) "
                          "instead of autotuning")
@@ -499,6 +529,10 @@ def main():
     if not args.no_sampling:
         progress("shot sampling")
         out["sampling"] = sampling(dev)
+        torch.cuda.empty_cache()
+    if not args.no_telegate:
+        progress("TeleGate trajectory")
+        out["telegate"] = telegate(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")

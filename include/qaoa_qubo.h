@@ -332,6 +332,32 @@ qq_status qq_graph_read(qq_graph *graph, double *energy, double *grad, double *h
 qq_status qq_graph_destroy(qq_graph *graph);
 
 /*
+ * Gate-level trajectory of the distributed circuit with explicit TeleGate remote
+ * CNOTs (distributed circuit construction section): n data qubits plus two
+ * communication qubits, complex128, for the allocation set by
+ * qq_set_allocation.  Per layer: the phase of every QPU-local term (C minus the
+ * cross couplings, eq. (16)); each cross coupling b z_i z_j (i < j, row-major)
+ * as phases exp(-i gamma b / 2) on z_i = 1 and on z_j = 1 and the parity phase
+ * CNOT(i -> j) diag_j(1, e^{+i gamma b / 2}) CNOT(i -> j) with both CNOTs remote;
+ * then RX(2 beta) on every data qubit.  A remote CNOT entangles the
+ * communication pair, couples and measures one member on each QPU, corrects the
+ * data qubits (X on the target, Z on the control, conditioned on the outcomes)
+ * and resets the pair; the remaining global phase (-1)^(m1 m2) is removed, so
+ * every trajectory's data state equals the exact state of qq_state (complex128).
+ *   params        host [2p]
+ *   uniforms      host doubles in [0, 1), two per remote CNOT in circuit order
+ *                 (4 x cross x p); a measurement gives 1 when its uniform is
+ *                 below the probability of 1
+ *   psi_out       2^n complex128, host (device with QQ_OUT_ON_DEVICE)
+ *   outcomes_out  host int32 [2 x remote] measurement outcomes, or NULL
+ *   remote_out    remote CNOTs of the circuit, 2 x cross x p, or NULL
+ * n <= 26.  Errors: QQ_E_INVALID, QQ_E_ALLOCATION (no allocation),
+ * QQ_E_TOO_LARGE, QQ_E_NOMEM, QQ_E_DEVICE.
+ */
+qq_status qq_telegate_state(qq_problem *prob, int p, const double *params, const double *uniforms, int flags,
+                            void *psi_out, int32_t *outcomes_out, int64_t *remote_out, void *stream);
+
+/*
  * Variable-to-QPU allocation (multi-QPU variable allocation section, Fig. 1).
  * Host-only functions of the dense input form (H as for qq_problem_create, n x n
  * row-major host array); they need no device and feed qq_set_allocation.

@@ -43,6 +43,7 @@ qq_status fail(qq_status st, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(QQ_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+constexpr int kTelegateMaxN = 26;  // n + 2 qubits of complex128: 4 GiB
 constexpr double kTwo31 = 2147483648.0;
 // The specialised kernels serve every n up to QQ_MAX_N: a lane's amplitudes are addressed with a
 // 32-bit byte offset of at most (15 + 3 * 2^pos8) * 8 bytes while pos8 <= 27, and with a 64-bit one
@@ -1507,6 +1508,91 @@ qq_status qq_state(qq_problem *pb, int p, const double *params, int flags, void 
     QQ_HIP(hipMemcpyAsync(psi_out, static_cast<char *>(own.p) + L.psi, bytes,
                           (flags & QQ_OUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
     QQ_HIP(hipStreamSynchronize(stream));
+    return QQ_OK;
+}
+
+qq_status qq_telegate_state(qq_problem *pb, int p, const double *params, const double *uniforms, int flags,
+                            void *psi_out, int32_t *outcomes_out, int64_t *remote_out, void *stream_)
+{
+    g_err.clear();
+    if (!pb || !params || !psi_out) return fail(QQ_E_INVALID, "problem / params / psi_out is NULL");
+    if (p < 1 || p > QQ_MAX_P) return fail(QQ_E_INVALID, "p = %d outside [1, %d]", p, QQ_MAX_P);
+    if (flags & ~QQ_OUT_ON_DEVICE) return fail(QQ_E_INVALID, "flags 0x%x: only QQ_OUT_ON_DEVICE applies", flags);
+    if (pb->num_qpus < 1 || !pb->d_cross) return fail(QQ_E_ALLOCATION, "no allocation set (qq_set_allocation)");
+    if (pb->n > kTelegateMaxN) return fail(QQ_E_TOO_LARGE, "n = %d: the trajectory holds n + 2 qubits, n <= %d", pb->n, kTelegateMaxN);
+    if (qq_status st = check_params_host(params, 2 * (size_t)p); st != QQ_OK) return st;
+    // cross-QPU couplings, row-major (pairs are stored in that order)
+    std::vector<int> ci, cj;
+    std::vector<double> cb;
+    for (size_t k = 0; k < pb->pair_b.size(); ++k) {
+        const int i = pb->pair_ij[2 * k], j = pb->pair_ij[2 * k + 1];
+        if (pb->qpu[i] != pb->qpu[j]) {
+            ci.push_back(i);
+            cj.push_back(j);
+            cb.push_back(pb->pair_b[k]);
+        }
+    }
+    const int64_t nremote = 2 * (int64_t)ci.size() * p, nmeas = 2 * nremote;
+    if (nmeas > 0 && !uniforms) return fail(QQ_E_INVALID, "uniforms is NULL (%lld needed)", (long long)nmeas);
+    for (int64_t i = 0; i < nmeas; ++i)
+        if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0))
+            return fail(QQ_E_INVALID, "uniforms[%lld] = %g is not in [0, 1)", (long long)i, uniforms[i]);
+    const int n = pb->n, nq = n + 2, ca = n, cbq = n + 1;
+    const uint64_t dim = 1ull << nq;
+    const int nblocks = 256;
+    const size_t o_part = align_up(dim * 16), o_out = o_part + align_up(nblocks * 8),
+                 o_scale = o_out + align_up(std::max<int64_t>(1, nmeas) * 4), total = o_scale + align_up(std::max<int64_t>(1, nmeas) * 8);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(pb->device));
+    if (qq_status st = check_device_fits(pb->device, total, "the trajectory state"); st != QQ_OK) return st;
+    DevBuf buf;
+    if (hipMalloc(&buf.p, total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) failed", total);
+    char *b = static_cast<char *>(buf.p);
+    double2 *psi = reinterpret_cast<double2 *>(b);
+    double *partial = reinterpret_cast<double *>(b + o_part);
+    int *outcome = reinterpret_cast<int *>(b + o_out);
+    double *scale = reinterpret_cast<double *>(b + o_scale);
+    int slot = 0;
+    // remote CNOT(c -> t): entangle the communication pair, couple and measure each side, correct the
+    // data qubits (X^m1 on t, Z^m2 on c), reset the pair and remove the global phase (-1)^(m1 m2)
+    auto remote_cnot = [&](int c, int t) -> qq_status {
+        QQ_HIP(tg_launch_pair(psi, nq, ca, 1, 0, 0, 0, outcome, 0, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, cbq, 0, ca, 0, 0, outcome, 0, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, ca, 0, c, 0, 0, outcome, 0, stream));
+        QQ_HIP(tg_launch_measure(psi, nq, ca, uniforms[slot], partial, nblocks, outcome, scale, slot, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, t, 0, cbq, 0, 0, outcome, 0, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, cbq, 1, 0, 0, 0, outcome, 0, stream));
+        QQ_HIP(tg_launch_measure(psi, nq, cbq, uniforms[slot + 1], partial, nblocks, outcome, scale, slot + 1, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, t, 3, 0, 0, 0, outcome, slot, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, c, 4, 0, 0, 0, outcome, slot + 1, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, ca, 3, 0, 0, 0, outcome, slot, stream));
+        QQ_HIP(tg_launch_pair(psi, nq, cbq, 3, 0, 0, 0, outcome, slot + 1, stream));
+        QQ_HIP(tg_launch_sign(psi, nq, outcome, slot, stream));
+        slot += 2;
+        return QQ_OK;
+    };
+    QQ_HIP(tg_launch_init(psi, n, stream));
+    for (int k = 0; k < p; ++k) {
+        const double g = params[2 * k], be = params[2 * k + 1];
+        QQ_HIP(tg_launch_local_phase(psi, n, pb->d_diag, pb->d_cross, pb->diag_type, g, stream));
+        for (size_t x = 0; x < ci.size(); ++x) {
+            // exp(-i g b z_i z_j) = phases exp(-i g b / 2) on z_i = 1 and on z_j = 1, and the parity phase
+            // exp(+i g b (z_i xor z_j) / 2) = CNOT(i -> j) diag_j(1, e^{+i g b / 2}) CNOT(i -> j)
+            QQ_HIP(tg_launch_phase1(psi, nq, ci[x], -g * cb[x] / 2.0, stream));
+            QQ_HIP(tg_launch_phase1(psi, nq, cj[x], -g * cb[x] / 2.0, stream));
+            if (qq_status st = remote_cnot(ci[x], cj[x]); st != QQ_OK) return st;
+            QQ_HIP(tg_launch_phase1(psi, nq, cj[x], g * cb[x] / 2.0, stream));
+            if (qq_status st = remote_cnot(ci[x], cj[x]); st != QQ_OK) return st;
+        }
+        for (int q = 0; q < n; ++q) QQ_HIP(tg_launch_pair(psi, nq, q, 2, 0, std::cos(be), std::sin(be), outcome, 0, stream));
+    }
+    // the data register with the communication pair in |00>
+    QQ_HIP(hipMemcpyAsync(psi_out, psi, ((size_t)1 << n) * 16,
+                          (flags & QQ_OUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
+    if (outcomes_out && nmeas > 0)
+        QQ_HIP(hipMemcpyAsync(outcomes_out, outcome, (size_t)nmeas * 4, hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    if (remote_out) *remote_out = nremote;
     return QQ_OK;
 }
 

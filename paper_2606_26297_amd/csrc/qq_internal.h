@@ -224,6 +224,19 @@ hipError_t launch_shots(const void *psi, bool c128, uint64_t dim, uint64_t nblk,
 hipError_t launch_gather_cost(const void *diag, int diag_type, const uint64_t *idx, int64_t count, double *out,
                               hipStream_t s);
 
+// Gate-level TeleGate trajectory (qq_telegate.hip), complex128 over n + 2 qubits.  tg_launch_pair
+// kinds: 0 CNOT(c -> t), 1 H(t), 2 RX(2 beta)(t) with (cos, sin), 3 X(t) if outcome[slot],
+// 4 Z(t) if outcome[slot].
+hipError_t tg_launch_init(double2 *psi, int n, hipStream_t s);
+hipError_t tg_launch_local_phase(double2 *psi, int n, const void *diag, const void *cross, int diag_type, double gamma,
+                                 hipStream_t s);
+hipError_t tg_launch_phase1(double2 *psi, int nq, int q, double phi, hipStream_t s);
+hipError_t tg_launch_pair(double2 *psi, int nq, int t, int kind, int c, double cb, double sb, const int *outcome,
+                          int slot, hipStream_t s);
+hipError_t tg_launch_measure(double2 *psi, int nq, int q, double u, double *partial, int nblocks, int *outcome,
+                             double *scale, int slot, hipStream_t s);
+hipError_t tg_launch_sign(double2 *psi, int nq, const int *outcome, int slot, hipStream_t s);
+
 // Host helpers shared with the driver (qq_api.cpp): record the thread's error message; the
 // device a problem lives on.
 qq_status set_error(qq_status st, const char *msg);

@@ -135,6 +135,7 @@ SIGNATURES = {
     "qq_sample": ([_vp, _int, _vp, _int, ctypes.c_int64, _vp, _vp, _vp], _int),
     "qq_sample_stats": ([_vp, ctypes.c_int64, _u64p, ctypes.c_double, _int, _vp, ctypes.POINTER(QQSampleStats), _u64p,
                          _i64p, _dp], _int),
+    "qq_telegate_state": ([_vp, _int, _dp, _dp, _int, _vp, _i32p, _i64p, _vp], _int),
     "qq_balanced_capacities": ([_int, _int, _vp], _int),
     "qq_allocation": ([_int, _dp, _int, _vp, _int, _i32p, _i64p], _int),
     "qq_allocation_candidates": ([_int, _dp, _int, _vp, _i32p, _int, _i32p, _i64p, _i64p, ctypes.POINTER(_int),
@@ -440,6 +441,20 @@ def qq_sample_stats(handle, indices, margin=0.0, k=10, stream=None):
     d = {name: getattr(st, name) for name, _ in QQSampleStats._fields_}
     d["elite_index"], d["elite_count"], d["elite_cost"] = ei[:st.elite], ec[:st.elite], eco[:st.elite]
     return d
+
+
+def qq_telegate_state(handle, n, params, uniforms, stream=None):
+    """(data state [2^n] complex128, measurement outcomes, remote CNOT count) of one trajectory of the
+    distributed circuit with explicit TeleGate remote CNOTs."""
+    params = np.ascontiguousarray(params, dtype=np.float64).ravel()
+    u = np.ascontiguousarray(uniforms, dtype=np.float64).ravel()
+    psi = np.empty(1 << n, dtype=np.complex128)
+    outcomes = np.zeros(max(1, 2 * u.size), dtype=np.int32)
+    remote = ctypes.c_int64(0)
+    _check(lib().qq_telegate_state(handle, params.size // 2, params.ctypes.data_as(_dp),
+                                   u.ctypes.data_as(_dp) if u.size else None, 0, psi.ctypes.data_as(_vp),
+                                   outcomes.ctypes.data_as(_i32p), ctypes.byref(remote), _stream_ptr(stream)))
+    return psi, outcomes[:2 * remote.value], remote.value
 
 
 QQ_ALLOC_CONTIGUOUS = 0
