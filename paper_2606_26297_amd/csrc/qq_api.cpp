@@ -124,6 +124,9 @@ struct qq_problem {
     // the pass kernels: regq[16 q + r] = sum over the bits k > j of r of b_{R_j R_k}, j the lowest
     // bit of r (0 for r = 0 and single bits); q = 0 .. n - 4.
     double *d_regq = nullptr;
+    // The same sums per factor of the partitioned phase (set by qq_set_allocation): [factor][q][16],
+    // factors 0 .. M-1 the QPU-local couplings, factor M the cross-QPU couplings.
+    double *d_part_cq = nullptr;
     // summary
     double alpha = 0, sigma_c = 0, cmin = 0, cmax = 0;
     uint64_t argmin = 0;
@@ -147,7 +150,8 @@ struct qq_problem {
 
     ~qq_problem()
     {
-        void *ptrs[] = {d_diag, d_ell, d_ell_i, d_pair_ij, d_pair_b, d_pair_bi, d_regq, d_qpu, d_tables, d_cross, d_part};
+        void *ptrs[] = {d_diag, d_ell, d_ell_i, d_pair_ij, d_pair_b, d_pair_bi, d_regq, d_part_cq, d_qpu, d_tables, d_cross,
+                        d_part};
         if (dim) (void)hipSetDevice(device);
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
@@ -519,8 +523,12 @@ double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128, bo
             diag_reads += 1;
         if ((o.kind == OP_PHASE || (o.kind == OP_GGAMMA && (o.flags & OPF_UNPHASE))) && part) cross_reads += 1;
     }
-    // the specialised kernels read 5 of every 16 diagonal entries and form the rest from them
-    if (fast) diag_reads *= 5.0 / 16.0;
+    // the specialised kernels read 5 of every 16 diagonal (and cross-diagonal) entries and form the
+    // rest from them
+    if (fast) {
+        diag_reads *= 5.0 / 16.0;
+        cross_reads *= 5.0 / 16.0;
+    }
     return (double)pb->dim * (B * moves * es + (diag_reads + cross_reads) * d);
 }
 
@@ -604,6 +612,8 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             fp.state_stride = pb->dim;
             fp.partial = a.partial;
             fp.cq = pb->d_regq + 16 * (pp.fkind == FK_FIRST ? sd.pos8 : sd.pos4);
+            fp.part_cq = pb->d_part_cq;
+            fp.part_cq_runs = std::max(1, pb->n - 3);
             QQ_HIP(launch_fast_pass(pp.fkind, sd.high != 0, pb->diag_type, fp, stream));
         } else {
             QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
@@ -1376,9 +1386,10 @@ qq_status qq_set_allocation(qq_problem *pb, int M, const int32_t *qpu_of_var, co
         return st;
     QQ_HIP(hipSetDevice(pb->device));
     // release a previous allocation
-    void *olds[] = {pb->d_qpu, pb->d_tables, pb->d_cross, pb->d_part};
+    void *olds[] = {pb->d_qpu, pb->d_tables, pb->d_cross, pb->d_part, pb->d_part_cq};
     for (void *q : olds)
         if (q) QQ_HIP(hipFree(q));
+    pb->d_part_cq = nullptr;
     pb->d_qpu = nullptr;
     pb->d_tables = pb->d_cross = nullptr;
     pb->d_part = nullptr;
@@ -1389,6 +1400,26 @@ qq_status qq_set_allocation(qq_problem *pb, int M, const int32_t *qpu_of_var, co
     if (hipMalloc(&pb->d_cross, (size_t)pb->dim * es) != hipSuccess)
         return fail(QQ_E_NOMEM, "hipMalloc for the cross diagonal failed");
     QQ_HIP(hipMalloc((void **)&pb->d_part, sizeof(PartDesc)));
+    {
+        // pair sums of every factor among each run of four consecutive qubits (see d_part_cq)
+        const int runs = std::max(1, n - 3);
+        std::vector<double> pcq((size_t)(M + 1) * runs * 16, 0.0);
+        for (int f = 0; f <= M; ++f)
+            for (int q = 0; q + 4 <= n; ++q)
+                for (int r = 1; r < 16; ++r) {
+                    const int j = __builtin_ctz(r), a = q + j;
+                    double sum = 0.0;
+                    for (int k = j + 1; k < 4; ++k) {
+                        if (!((r >> k) & 1)) continue;
+                        const int c = q + k;
+                        const bool local = qpu_of_var[a] == qpu_of_var[c];
+                        if ((f == M && !local) || (f < M && local && qpu_of_var[a] == f)) sum += pb->b[(size_t)a * n + c];
+                    }
+                    pcq[((size_t)f * runs + q) * 16 + r] = sum;
+                }
+        QQ_HIP(hipMalloc((void **)&pb->d_part_cq, sizeof(double) * pcq.size()));
+        QQ_HIP(hipMemcpy(pb->d_part_cq, pcq.data(), sizeof(double) * pcq.size(), hipMemcpyHostToDevice));
+    }
     QQ_HIP(hipMemcpy(pb->d_qpu, qpu_of_var, sizeof(int32_t) * n, hipMemcpyHostToDevice));
     QQ_HIP(hipMemcpy(pb->d_part, &pd, sizeof(PartDesc), hipMemcpyHostToDevice));
     QQ_HIP(launch_local_tables(n, pb->diag_type, pb->d_part, pb->d_ell, pb->d_ell_i, (int)pb->pair_b.size(),

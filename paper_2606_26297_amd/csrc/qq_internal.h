@@ -152,6 +152,9 @@ struct FastPassParams {
     // device [16]: sums of the couplings among the register qubits of the layout in which the pass
     // reads the diagonal (regq of the problem at that layout's register run)
     const double *cq;
+    // partitioned phases: the same sums per factor, [factor (local QPUs, then cross)][run start][16]
+    const double *part_cq;
+    int part_cq_runs;
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
 

@@ -243,6 +243,8 @@ __device__ __forceinline__ void run_chunk(const ManyInst &I, const ManyPass &P, 
     a.tables = nullptr;
     a.cross = nullptr;
     a.cq = I.regq + 16 * (P.kind == FK_FIRST ? P.pos8 : P.pos4);
+    a.pcq = nullptr;  // the persistent launch takes no partitioned phases
+    a.pcq_runs = 0;
     double acc[3] = {0.0, 0.0, 0.0};
     const int g = (int)t0;
     switch (P.kind) {

@@ -391,6 +391,8 @@ struct FastArgs {
     const void *tables;    // packed per-QPU local tables
     const void *cross;     // cross-QPU diagonal, 2^n entries
     const double *cq;      // 16 pair sums of the register qubits of the layout the diagonal is read in
+    const double *pcq;     // partitioned: pair sums of every factor, [factor][run start][16]
+    int pcq_runs;          // run starts per factor (n - 3)
 };
 
 // ---- partitioned phase (eq. (16)) --------------------------------------------------------------
@@ -438,8 +440,11 @@ __device__ __forceinline__ uint32_t part_gather(uint64_t zb, uint64_t vmask)
 // term reduced on its own in FP64 to [-1/2, 1/2], the sum reduced again and rounded to float.
 // Layout: lanes hold qubits 0..3 (lane_lo) and qh, qh + 1 (lane_hi); registers hold qubits
 // qr..qr+3 (register stride rs); zb is the tile's wave-uniform first index; vd the lane's byte
-// offset into a DT diagonal.  The angles do not depend on the state, so a pass can form them
-// before it loads any amplitude.
+// offset into a DT diagonal.  Every factor is quadratic in z, so its 16 register values follow from
+// five reads (register 0 and the four single-bit registers) and the factor's pair sums among the
+// register qubits (a.pcq, laid out [factor][run start][16], the cross factor last), as for the
+// cost diagonal.  The angles do not depend on the state, so a pass can form them before it loads
+// any amplitude.
 template <typename DT, typename O>
 __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &a, double g2pi, uint64_t zb,
                                             uint32_t lane_lo, uint32_t lane_hi, int qh, int qr, uint64_t rs, O vd)
@@ -452,15 +457,34 @@ __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &
     const uint64_t cross_a = (uint64_t)a.cross;
     const int M = a.part->nparts;
     const DT *tables = static_cast<const DT *>(a.tables);
+    RegQ *pcq = (RegQ *)a.pcq;
+    // the five values of one factor -> its 8 register values of half h, reduced and added to u
+    auto add_factor = [&](const double (&e)[5], RegQ *w, int h, double (&u)[H], bool first) {
+        double k[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[j] = e[j + 1] - e[0];
+        double v[H];
+        v[0] = h ? e[4] : e[0];
+#pragma unroll
+        for (int i = 1; i < H; ++i) {
+            const int j = __builtin_ctz(i);
+            v[i] = (v[i - (1 << j)] + k[j]) + w[h * H + i];
+        }
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double x = g2pi * v[i];
+            u[i] = first ? x - rint(x) : u[i] + (x - rint(x));
+        }
+    };
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         double u[H];
+        {
+            double e[5];
+            e[0] = (double)gld<DT>(cross_a + zb * sizeof(DT), vd);
 #pragma unroll
-        for (int i = 0; i < H; ++i) {
-            const int r = h * H + i;
-            const double w = g2pi * (double)gld<DT>(cross_a + (zb + r * rs) * sizeof(DT), vd);
-            u[i] = w - rint(w);
-            QQ_CHUNK_FENCE(i);
+            for (int j = 0; j < 4; ++j) e[j + 1] = (double)gld<DT>(cross_a + (zb + (rs << j)) * sizeof(DT), vd);
+            add_factor(e, pcq + ((size_t)M * a.pcq_runs + qr) * kRegs, h, u, true);
         }
         for (int m = 0; m < M; ++m) {
             const uint64_t vm = a.part->vmask[m];
@@ -470,17 +494,12 @@ __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &
             for (int j = 0; j < 4; ++j) L += ((lane_lo >> j) & 1u) ? part_contrib(vm, j) : 0u;
             L += (lane_hi & 1u) ? part_contrib(vm, qh) : 0u;
             L += (lane_hi & 2u) ? part_contrib(vm, qh + 1) : 0u;
-            const uint32_t c0 = part_contrib(vm, qr), c1 = part_contrib(vm, qr + 1), c2 = part_contrib(vm, qr + 2),
-                           c3 = part_contrib(vm, qr + 3);
+            double e[5];
+            e[0] = (double)gld<DT>(tab, L * (uint32_t)sizeof(DT));
 #pragma unroll
-            for (int i = 0; i < H; ++i) {
-                const int r = h * H + i;
-                const uint32_t idx =
-                    L + ((r & 1) ? c0 : 0u) + ((r & 2) ? c1 : 0u) + ((r & 4) ? c2 : 0u) + ((r & 8) ? c3 : 0u);
-                const double w = g2pi * (double)gld<DT>(tab, idx * (uint32_t)sizeof(DT));
-                u[i] += w - rint(w);
-                QQ_CHUNK_FENCE(i);
-            }
+            for (int j = 0; j < 4; ++j)
+                e[j + 1] = (double)gld<DT>(tab, (L + part_contrib(vm, qr + j)) * (uint32_t)sizeof(DT));
+            add_factor(e, pcq + ((size_t)m * a.pcq_runs + qr) * kRegs, h, u, false);
         }
 #pragma unroll
         for (int i = 0; i < H; ++i) uf[h * H + i] = (float)(u[i] - rint(u[i]));
