@@ -377,7 +377,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the hot path of this build runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not built). Run with --gpus 1.", file=sys.stderr)
+              "(sharding over several GPUs is not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
