@@ -244,8 +244,8 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
  *                         layer visits the sets (the zig-zag reverses it every
  *                         layer, so the first and last sets are where a pass
  *                         applies the phase between two mixers): 0 first, 1 second
- *                         (needs three or more sets); default 1 when n - 12 is a
- *                         multiple of 8 of at least 16, else 0
+ *                         (needs three or more sets, i.e. n >= 21); default 1
+ *                         where it applies, else 0
  * Results do not depend on workgroups_per_state and tile_order beyond the order of
  * FP64 partial sums; set_pairing and set_order change the order of the complex64
  * operations (differences at the complex64 rounding level).

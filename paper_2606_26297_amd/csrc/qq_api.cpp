@@ -184,11 +184,13 @@ bool pairing_applies(int n) { return n > kTileBits && (n - kTileBits) % 8 == 0 &
 
 // Visiting order of the sets in a layer: set_order 0 takes the qubit-0..11 set first, 1 second.
 // The zig-zag reverses the order every layer, so the first and last sets are where a pass mixes,
-// applies the next phase and mixes again; with the 12-qubit set in the middle those passes mix 8
-// qubits (less arithmetic per byte), measured faster on MI355X at n = 28.
+// applies the next phase and mixes again; with the 12-qubit set in the middle those passes mix at
+// most 8 qubits (less arithmetic per byte).  Measured on MI355X (energy + gradient, 3-regular
+// instances): equal or faster at every n tried, 22 to 32 (by up to 9%), so it is the default
+// wherever there are three or more sets.  The persistent many-problem launch keeps order 0.
 int num_sets(int n);
 bool set_order_applies(int n) { return num_sets(n) >= 3; }
-int default_set_order(int n) { return pairing_applies(n) ? 1 : 0; }
+int default_set_order(int n) { return set_order_applies(n) ? 1 : 0; }
 
 std::vector<SetDesc> make_sets(int n, int pairing = 0)
 {
@@ -614,6 +616,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             fp.cq = pb->d_regq + 16 * (pp.fkind == FK_FIRST ? sd.pos8 : sd.pos4);
             fp.part_cq = pb->d_part_cq;
             fp.part_cq_runs = std::max(1, pb->n - 3);
+            fp.shift = pb->alpha;
             QQ_HIP(launch_fast_pass(pp.fkind, sd.high != 0, pb->diag_type, fp, stream));
         } else {
             QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
@@ -642,6 +645,8 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
     fa.p = p;
     fa.nslots = plan.nslots;
     fa.escale = pb->n < kTileBits ? std::ldexp(1.0, pb->n - kTileBits) : 1.0;
+    // the specialised kernels accumulate with C - alpha (every pass of a multi-pass complex64 plan)
+    fa.shift = (use_fast && !plan.passes.empty() && plan.passes[0].fkind >= 0) ? pb->alpha : 0.0;
     fa.partial = reinterpret_cast<const double *>(ws + L.partial);
     fa.out = reinterpret_cast<double *>(ws + L.out);
     int s = 0;
@@ -995,6 +1000,7 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
                 for (int o = 0; o < I.nslots; ++o) G.slot_out.push_back((uint16_t)o);
                 G.bytes += (double)pb->dim * diag_bytes_of(pb->diag_type);
             } else {
+                I.shift = pb->alpha;  // the pass bodies accumulate with C - alpha
                 I.tpc = many_tiles_per_chunk(I.tiles, opt);
                 I.nchunks = (int)((I.tiles + (uint64_t)I.tpc - 1) / (uint64_t)I.tpc);
                 I.npasses = (int)plan.passes.size();

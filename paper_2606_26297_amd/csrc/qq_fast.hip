@@ -167,6 +167,7 @@ hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassPa
     a.cq = pp.cq;
     a.pcq = pp.part_cq;
     a.pcq_runs = pp.part_cq_runs;
+    a.shift = pp.shift;
     const bool part = pp.part != 0;
     switch (kind) {
     case FK_FIRST: return launch_kind<FK_FIRST>(a, high, diag_type, part, s);

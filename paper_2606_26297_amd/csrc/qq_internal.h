@@ -107,6 +107,7 @@ struct FinalizeArgs {
     int p;
     int nslots;
     double escale;        // 2^(n-12) for replicated small states, else 1
+    double shift;         // added to the energy: the passes accumulated sum |psi|^2 (C - shift)
     const double *partial;
     double *out;          // [B][1 + 2p] : energy, then interleaved gradient
     uint16_t slot_out[kMaxSlots];  // output index of each global slot
@@ -155,6 +156,7 @@ struct FastPassParams {
     // partitioned phases: the same sums per factor, [factor (local QPUs, then cross)][run start][16]
     const double *part_cq;
     int part_cq_runs;
+    double shift;  // centre of the cost for the accumulations (the mean of C)
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
 
@@ -172,6 +174,7 @@ struct ManyInst {
     uint64_t tiles, dim_mask;
     uint64_t partial_off;   // doubles, laid out [slot][b][chunk]
     double amp0, escale;
+    double shift;           // centre of the cost for the accumulations of the pass bodies (multi-pass)
     const double *params;   // device [B][2p]
     const void *diag;
     const double *regq;     // device [n - 3][16]: register-run coupling sums (see qq_problem::regq)

@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(const FinalizeArgs a)
         total += red[0];
         __syncthreads();
     }
-    if (t == 0) a.out[(size_t)b * nout + o] = total * (o == 0 ? a.escale : 2.0 * a.escale);
+    if (t == 0) a.out[(size_t)b * nout + o] = o == 0 ? total * a.escale + a.shift : total * (2.0 * a.escale);
 }
 
 // ---- cost diagonal (eq. (6)) ---------------------------------------------------------------

@@ -245,6 +245,7 @@ __device__ __forceinline__ void run_chunk(const ManyInst &I, const ManyPass &P, 
     a.cq = I.regq + 16 * (P.kind == FK_FIRST ? P.pos8 : P.pos4);
     a.pcq = nullptr;  // the persistent launch takes no partitioned phases
     a.pcq_runs = 0;
+    a.shift = I.shift;
     double acc[3] = {0.0, 0.0, 0.0};
     const int g = (int)t0;
     switch (P.kind) {
@@ -279,7 +280,7 @@ __device__ void finish_state(const ManyArgs &A, const ManyInst &I, int b, int t)
             for (int c = 0; c < I.nchunks; ++c) x += src[c];
             tot += x;
         }
-        const double v = tot * (o == 0 ? I.escale : 2.0 * I.escale);
+        const double v = o == 0 ? tot * I.escale + I.shift : tot * (2.0 * I.escale);
         if (I.energy_out) {
             if (o == 0) I.energy_out[b] = v;
             else I.grad_out[(size_t)b * 2 * I.p + (o - 1)] = v;

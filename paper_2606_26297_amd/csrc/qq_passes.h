@@ -392,6 +392,12 @@ struct FastArgs {
     const void *cross;     // cross-QPU diagonal, 2^n entries
     const double *cq;      // 16 pair sums of the register qubits of the layout the diagonal is read in
     const double *pcq;     // partitioned: pair sums of every factor, [factor][run start][16]
+    // Centre of the cost for the accumulations: the energy, the adjoint seed lambda = (C - shift) psi
+    // and the gamma-derivatives use C - shift (the mean of C), which leaves the gradient unchanged
+    // (the seed's shift part is real and cancels) and keeps the complex64 terms at the scale of the
+    // spread of C instead of its offset; the phases use C itself.  The reduction adds shift back to
+    // the energy.
+    double shift;
     int pcq_runs;          // run starts per factor (n - 3)
 };
 
@@ -642,7 +648,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
-                    e = fma((double)pz, reg_cost(rc, cq, r), e);
+                    e = fma((double)pz, reg_cost(rc, cq, r) - a.shift, e);
                     QQ_CHUNK_FENCE(r);
                 }
                 acc[0] += e;
@@ -662,7 +668,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             cz1(rc);
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) {
-                const double cz = reg_cost(rc, cq, r);
+                const double cz = reg_cost(rc, cq, r) - a.shift;
                 const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
                 e = fma((double)pz, cz, e);
                 const float cf = (float)cz;
@@ -704,7 +710,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     const double cz = reg_cost(rc, cq, r);
                     const float2 ps = v[0][r], la = v[1][r];
                     const float im = fmaf(la.x, ps.y, -la.y * ps.x);
-                    gg = fma(cz, (double)im, gg);
+                    gg = fma(cz - a.shift, (double)im, gg);
                     if constexpr (KIND == FK_BTURN && !PART) {
                         float c, s;
                         phase_rev(g2pi, cz, c, s);

@@ -68,6 +68,19 @@ def test_mix_covers_every_diagonal_type(mix):
     assert sorted({pb.info.diag_bytes for pb in pbs}) == [2, 4, 8]
 
 
+def per_problem_same_order(pb, x):
+    """pb.evaluate with the set order of the persistent launch (the qubit-0..11 set first), so the two
+    paths run the same complex64 operations."""
+    p, B = x.shape[1] // 2, x.shape[0]
+    flags = N.QQ_ENERGY | N.QQ_GRAD
+    G = N.qq_get_schedule(pb.handle, p, B, flags)["workgroups_per_state"]
+    N.qq_set_schedule(pb.handle, p, B, flags, {"workgroups_per_state": G, "set_order": 0})
+    try:
+        return pb.evaluate(x, grad=True)
+    finally:
+        N.qq_set_schedule(pb.handle, p, B, flags, None)
+
+
 def test_many_vs_oracle_and_per_problem(mix):
     insts, pbs = mix
     xs = [x for _, x in insts]
@@ -76,8 +89,8 @@ def test_many_vs_oracle_and_per_problem(mix):
         n = pb.n
         sig = pb.info.sigma_c
         print(f"problem {k}: n={n} p={x.shape[1] // 2} B={x.shape[0]}", flush=True)
-        # per-problem launches
-        e1, g1 = pb.evaluate(x, grad=True)
+        # per-problem launches (same set order)
+        e1, g1 = per_problem_same_order(pb, x)
         tol = 1e-9 if n > 12 else 1e-5
         assert e_err(e[k], e1, sig) <= tol, (k, e[k], e1)
         assert g_err(g[k], g1) <= tol, k
@@ -168,38 +181,45 @@ def test_many_wait_limit_reports_error_then_recovers(mix):
     assert ei.value.status == N.QQ_E_DEVICE
     e, g = evaluate_many(sub, xs, grad=True)
     for k, pb in zip(big, sub):
-        e1, g1 = pb.evaluate(insts[k][1], grad=True)
+        e1, g1 = per_problem_same_order(pb, insts[k][1])
         assert e_err(e[big.index(k)], e1, pb.info.sigma_c) <= 1e-9
 
 
 def test_workload4_many_vs_per_problem_launches():
     """The uneven-batch workload (512 dense integer problems, n in 10..22, p in 1..6):
-    one persistent launch against 512 per-problem qq_evaluate calls, and the oracle
-    on a sample of the small problems."""
+    one persistent launch against 512 per-problem qq_evaluate calls (same operations), and the
+    oracle on every 16th problem (both paths) and on 24 small problems."""
     items = W.workload4()
     pbs = [Problem(i.H, i.f, i.c0) for i, _ in items]
     xs = [x for _, x in items]
     e, g = evaluate_many(pbs, xs, grad=True)
-    # both paths are complex64 (each within 1e-5 of FP64): they agree to 2e-5, and the
-    # problem where they differ most is checked against the oracle on both sides
+    # with the same set order both paths run the same complex64 pass bodies for n > 12 (1e-9); for
+    # n <= 12 the persistent launch evaluates the whole problem in one tile and the per-problem call
+    # runs the generic single-pass kernel, two complex64 codes (2e-5); every 16th
+    # problem is checked against the oracle on both sides, the gradient against
+    # 1e-5 * max(|g|_inf, 1e-2 sigma_C): complex64 rounding leaves errors near 1e-7 sigma_C in
+    # absolute terms, which is more than 1e-5 |g| when the gradient is small next to the spread of C
+    # (several p = 1 instances here)
     de, dg = [], []
-    per = []
     for k, ((inst, x), pb) in enumerate(zip(items, pbs)):
-        e1, g1 = pb.evaluate(x, grad=True)
-        per.append((e1, g1))
+        e1, g1 = per_problem_same_order(pb, x)
         de.append(e_err(e[k], e1, pb.info.sigma_c))
         dg.append(g_err(g[k], g1))
     print(f"workload4: many vs per-problem: worst energy rel {max(de):.3e}, worst grad rel {max(dg):.3e}", flush=True)
-    assert max(de) <= 2e-5 and max(dg) <= 2e-5
-    for k in sorted({int(np.argmax(de)), int(np.argmax(dg))}):
+    for k, pb in enumerate(pbs):
+        tol = 1e-9 if pb.n > 12 else 2e-5
+        assert de[k] <= tol and dg[k] <= tol, (k, pb.n, de[k], dg[k])
+    for k in range(0, len(items), 16):
         inst, x = items[k]
+        pb = pbs[k]
         d = O.cost_diagonal(inst.H, inst.f, inst.c0)
         er, gr = O.gradient(d, x[0])
-        sig = pbs[k].info.sigma_c
-        errs = (e_err(e[k][0], er, sig), g_err(g[k][0], gr), e_err(per[k][0][0], er, sig), g_err(per[k][1][0], gr))
-        print(f"  problem {k} (n={pbs[k].n}, p={x.shape[1] // 2}) vs oracle: many E {errs[0]:.2e} g {errs[1]:.2e}; "
-              f"per-problem E {errs[2]:.2e} g {errs[3]:.2e}", flush=True)
-        assert max(errs) <= 1e-5, (k, errs)
+        sig = pb.info.sigma_c
+        e1, g1 = pb.evaluate(x, grad=True)
+        scale = max(np.max(np.abs(gr)), 1e-2 * sig)
+        for ee, gg in ((e[k][0], g[k][0]), (e1[0], g1[0])):
+            assert e_err(ee, er, sig) <= 1e-5, k
+            assert np.max(np.abs(gg - gr)) <= 1e-5 * scale, (k, np.max(np.abs(gg - gr)) / scale)
     checked = 0
     for k, ((inst, x), pb) in enumerate(zip(items, pbs)):
         if pb.n > 16 or checked >= 24:
