@@ -589,6 +589,12 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         auto st2f = [&](uint64_t arr, int r, float2 x, uint64_t rs) { gst(arr + (b2 + r * rs) * 8, vs2, x); };
         auto st1f = [&](uint64_t arr, int r, float2 x, uint64_t rs) { gst(arr + (b1 + r * rs) * 8, vs1, x); };
 
+        // passes that read the cost after a mixer issue those reads with the state loads, so they
+        // are in flight during the mixer (the partitioned adjoint turn, at its register limit, and
+        // the first pass, which starts with the phase, read where they use them)
+        constexpr bool EARLY = KIND == FK_LAST || KIND == FK_LASTG || KIND == FK_BLAST ||
+                               ((KIND == FK_TURN || KIND == FK_BTURN) && !PART);
+        RegCost rc;
         if constexpr (KIND == FK_FIRST) {
             if constexpr (PART) {
                 float uf[kRegs];
@@ -597,7 +603,6 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 for (int r = 0; r < kRegs; ++r) v[0][r] = make_float2((float)a.amp0, 0.0f);
                 apply_angles<NS, 1, false>(v, uf);
             } else {
-                RegCost rc;
                 cz2(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
@@ -615,6 +620,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         } else if constexpr (KIND == FK_MID || KIND == FK_TURN || KIND == FK_LAST) {
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) v[0][r] = ld2(psi_a, r);
+            if constexpr (EARLY) cz1(rc);
             double unused = 0.0;
             mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
             if constexpr (KIND == FK_MID) {
@@ -627,8 +633,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     part_angles<DT>(uf, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, rs1, vd1);
                     apply_angles<NS, 1, false>(v, uf);
                 } else {
-                    RegCost rc;
-                    cz1(rc);
+                    if constexpr (!EARLY) cz1(rc);
 #pragma unroll
                     for (int r = 0; r < kRegs; ++r) {
                         float c, s;
@@ -643,8 +648,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 for (int r = 0; r < kRegs; ++r) st2f(psi_a, r, v[0][r], rss);
             } else {
                 double e = 0.0;
-                RegCost rc;
-                cz1(rc);
+                if constexpr (!EARLY) cz1(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
@@ -661,11 +665,10 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         } else if constexpr (KIND == FK_LASTG) {
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) v[0][r] = ld2(psi_a, r);
+            if constexpr (EARLY) cz1(rc);
             double gb = 0.0;
             mix_op<HIGH, FULL, 2, 2, 1, false, FB1>(lds, v, t, a.active, c1, gb);
             double e = 0.0;
-            RegCost rc;
-            cz1(rc);
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) {
                 const double cz = reg_cost(rc, cq, r) - a.shift;
@@ -691,6 +694,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 v[0][r] = ld2(psi_a, r);
                 v[1][r] = ld2(lam_a, r);
             }
+            if constexpr (EARLY) cz1(rc);
             double gb = 0.0;
             mix_op<HIGH, FULL, 2, 2, 3, true, FB1>(lds, v, t, a.active, c1, gb);
             acc[0] += gb;
@@ -703,8 +707,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 }
             } else {
                 double gg = 0.0;
-                RegCost rc;
-                cz1(rc);
+                if constexpr (!EARLY) cz1(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     const double cz = reg_cost(rc, cq, r);
