@@ -1670,9 +1670,13 @@ qq_status qq_sample(qq_problem *pb, int p, const double *params, int flags, int6
     QQ_HIP(hipMemcpyAsync(h.data(), d_mass, nblk * sizeof(double), hipMemcpyDeviceToHost, stream));
     QQ_HIP(hipStreamSynchronize(stream));
     start[0] = 0.0;
-    for (uint64_t i = 0; i < nblk; ++i) start[i + 1] = start[i] + h[i];
+    uint64_t last_blk = nblk - 1;  // the last block of nonzero mass (the last block if none has any)
+    for (uint64_t i = 0; i < nblk; ++i) {
+        start[i + 1] = start[i] + h[i];
+        if (h[i] > 0.0) last_blk = i;
+    }
     QQ_HIP(hipMemcpyAsync(d_start, start.data(), (nblk + 1) * sizeof(double), hipMemcpyHostToDevice, stream));
-    QQ_HIP(launch_shots(psi, c128, pb->dim, nblk, d_start, d_u, shots, d_out, stream));
+    QQ_HIP(launch_shots(psi, c128, pb->dim, nblk, d_start, last_blk, d_u, shots, d_out, stream));
     if (!dev_out)
         QQ_HIP(hipMemcpyAsync(indices_out, d_out, (size_t)shots * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
     QQ_HIP(hipStreamSynchronize(stream));

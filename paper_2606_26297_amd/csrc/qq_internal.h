@@ -225,8 +225,8 @@ hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
 
 // Shots from the exact distribution (qq_sample.hip).
 hipError_t launch_block_mass(const void *psi, bool c128, uint64_t dim, uint64_t nblk, double *mass, hipStream_t s);
-hipError_t launch_shots(const void *psi, bool c128, uint64_t dim, uint64_t nblk, const double *start, const double *u,
-                        int64_t shots, uint64_t *out, hipStream_t s);
+hipError_t launch_shots(const void *psi, bool c128, uint64_t dim, uint64_t nblk, const double *start,
+                        uint64_t last_blk, const double *u, int64_t shots, uint64_t *out, hipStream_t s);
 hipError_t launch_gather_cost(const void *diag, int diag_type, const uint64_t *idx, int64_t count, double *out,
                               hipStream_t s);
 

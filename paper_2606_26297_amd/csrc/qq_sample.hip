@@ -52,24 +52,33 @@ __global__ void __launch_bounds__(256) block_mass_kernel(const C2 *psi, uint64_t
     }
 }
 
-// One wave per shot.  start[b] = sum of the masses of blocks before b, start[nblk] = total.
+// One wave per shot.  start[b] = sum of the masses of blocks before b, start[nblk] = total;
+// last_blk: the last block of nonzero mass.
 template <typename C2>
 __global__ void __launch_bounds__(256) shot_kernel(const C2 *psi, uint64_t dim, uint64_t nblk, const double *start,
-                                                   const double *u, int64_t shots, uint64_t *out)
+                                                   uint64_t last_blk, const double *u, int64_t shots, uint64_t *out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const double total = start[nblk];
     for (int64_t s = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); s < shots; s += waves) {
-        const double t = u[s] * total;
-        // first block whose end exceeds t (the last block when rounding leaves none)
-        uint64_t lo = 0, hi = nblk - 1;
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (start[mid + 1] > t) hi = mid;
-            else lo = mid + 1;
+        const double us = u[s];
+        const double t = us * total;
+        uint64_t lo = last_blk;
+        double r = INFINITY;  // no entry reaches it: the scan below ends on the block's last nonzero entry
+        if (us >= 0.0 && t < total) {
+            // first block whose end exceeds t (at most last_blk, whose end is the total)
+            lo = 0;
+            uint64_t hi = last_blk;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (start[mid + 1] > t) hi = mid;
+                else lo = mid + 1;
+            }
+            r = t - start[lo];
         }
-        const double r = t - start[lo];
+        // uniforms outside [0, 1) (or whose product with the total rounds up to it) take the last
+        // index of nonzero probability
         const uint64_t base = lo * (uint64_t)(kRows * 64);
         uint64_t idx = base, last_pos = base;
         bool found = false;
@@ -121,16 +130,16 @@ hipError_t launch_block_mass(const void *psi, bool c128, uint64_t dim, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_shots(const void *psi, bool c128, uint64_t dim, uint64_t nblk, const double *start, const double *u,
-                        int64_t shots, uint64_t *out, hipStream_t s)
+hipError_t launch_shots(const void *psi, bool c128, uint64_t dim, uint64_t nblk, const double *start,
+                        uint64_t last_blk, const double *u, int64_t shots, uint64_t *out, hipStream_t s)
 {
     const dim3 grid(grid_for((uint64_t)shots)), block(256);
     if (c128)
         hipLaunchKernelGGL(shot_kernel<double2>, grid, block, 0, s, static_cast<const double2 *>(psi), dim, nblk, start,
-                           u, shots, out);
+                           last_blk, u, shots, out);
     else
         hipLaunchKernelGGL(shot_kernel<float2>, grid, block, 0, s, static_cast<const float2 *>(psi), dim, nblk, start,
-                           u, shots, out);
+                           last_blk, u, shots, out);
     return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@ C ABI).
   equals the oracle's index for at least 99.9% of the shots (all but boundary cases);
 * at full size (n = 28, p = 8, the benchmark instance) against a cumulative sum of the library's own
   probabilities in PyTorch FP64 (tolerance 1e-9);
+* device uniforms outside [0, 1) (and NaN) take the last index of nonzero probability, u = 0 the
+  first;
 * the metrics equal the oracle's on the same shots exactly (integer and real costs; same summation
   order);
 * validation.
@@ -80,6 +82,30 @@ def test_shots_full_size_n28_against_cumulative_probabilities():
         torch.cuda.empty_cache()
     finally:
         pb.close()
+
+
+@pytest.mark.parametrize("n", [10, 14])
+def test_device_uniforms_outside_the_unit_interval_take_the_last_nonzero_index(n):
+    """Device uniforms are not range-checked: values outside [0, 1), NaN, and one whose product with
+    the total probability rounds up to it take the last index of nonzero probability; u = 0 takes
+    the first (n = 10: one block with padding entries of zero probability; n = 14: four blocks)."""
+    import torch
+
+    inst = W.dense_gaussian_upper(n, 70)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    x = W.random_params(2, 1, 71)[0]
+    P = O.probabilities(O.qaoa_state(O.cost_diagonal(inst.H, inst.f, inst.c0), x))
+    last = int(np.flatnonzero(P > 0)[-1])
+    u = np.array([-0.1, 1.0, 1.5, np.nan, -np.inf, np.inf, np.nextafter(1.0, 0.0), 0.0])
+    for c128 in (True, False):
+        xt = torch.tensor(x, device="cuda:0")
+        ut = torch.tensor(u, device="cuda:0")
+        zt = torch.empty(u.size, dtype=torch.int64, device="cuda:0")
+        flags = N.QQ_PARAMS_ON_DEVICE | N.QQ_OUT_ON_DEVICE | (N.QQ_C128 if c128 else 0)
+        N.qq_sample(pb.handle, 2, xt, ut, flags, out=zt)
+        z = zt.cpu().numpy()
+        assert list(z[:7]) == [last] * 7, (c128, z)
+        assert z[7] == int(S.inverse_cdf(P, [0.0])[0]), (c128, z)
 
 
 @pytest.mark.parametrize("name,maker", [("int_n12", lambda: W.workload1()[0]),
