@@ -376,7 +376,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the hot path of this build runs on a single MI355X "
+        print("bench.py measures one GPU only: the library runs its hot path on a single MI355X "
               "(sharding over several GPUs is not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

@@ -50,7 +50,7 @@ typedef enum {
     QQ_E_WORKSPACE = -4,    /* caller workspace smaller than qq_workspace_size() */
     QQ_E_DEVICE = -5,       /* a HIP runtime call failed (message carries the HIP error string) */
     QQ_E_NOMEM = -6,        /* a device or host allocation failed */
-    QQ_E_UNSUPPORTED = -7   /* valid request this build does not support (message says which) */
+    QQ_E_UNSUPPORTED = -7   /* valid request the library does not support (message says which) */
 } qq_status;
 
 /* Flags for the evaluation calls (bitwise OR). */
