@@ -1,4 +1,6 @@
-"""Full-size (n = 28) GPU checks in the benchmark's launch configuration (16 states per call).
+"""Full-size (n = 28) GPU checks in the benchmark's launch configuration: complex64 calls of 64
+states (one wave) with the schedule the benchmark's autotuner picks on the MI355X (256 workgroups
+per state, blocked tile order, the qubit-0..11 set second), pinned here.
 
 The FP64 oracle cannot evaluate n = 28 one output at a time in test time, so
 these checks use results that hold at any size:
@@ -10,19 +12,34 @@ these checks use results that hold at any size:
 The blocks straddle every qubit-set boundary of the n = 28 pass plan
 (sets {0..11}, {12..15, 24..27}, {16..23}).
 Tolerance: 1e-5 relative for complex64 (energy |dE| / max(|E|, sigma_C),
-gradient ||dg||_inf / ||g||_inf), 1e-10 for complex128.
+gradient ||dg||_inf / max(||g||_inf, 1e-2 sigma_C)), 1e-10 for complex128 (gradient relative to
+||g||_inf).
 """
 import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_2606_26297_amd import native as NAT
 from paper_2606_26297_amd import workloads as W
 from paper_2606_26297_amd.qaoa import Problem
 
 pytestmark = pytest.mark.gpu
 
 N = 28
-WAVE = 16
+WAVE = 64
+BENCH_SCHEDULE = {"workgroups_per_state": 256, "set_pairing": 0, "tile_order": 1, "set_order": 1}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _free_cached_device_memory():
+    # a wave of 64 complex64 states with their adjoints takes 256 GiB of the 288 GB
+    import torch
+
+    torch.cuda.empty_cache()
+
+
+def pin_bench_schedule(pb, p):
+    NAT.qq_set_schedule(pb.handle, p, WAVE, NAT.QQ_ENERGY | NAT.QQ_GRAD, BENCH_SCHEDULE)
 
 
 def p1_qubit(ell, x):
@@ -52,8 +69,9 @@ def rel_e(e, eref, sigma):
     return np.max(np.abs(e - eref) / np.maximum(np.abs(eref), sigma))
 
 
-def rel_g(g, gref):
-    return max(np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(g, gref))
+def rel_g(g, gref, floor=0.0):
+    """max over states of ||g - gref||_inf / max(||gref||_inf, floor)."""
+    return max(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), floor) for a, b in zip(g, gref))
 
 
 @pytest.fixture(scope="module")
@@ -70,14 +88,18 @@ def test_separable_n28_energy_and_gradient(sep_problem, c128):
     p = 3
     B = 4 if c128 else WAVE
     x = W.random_params(p, B, 42)
+    if not c128:
+        pin_bench_schedule(pb, p)
     e, g = pb.evaluate(x, grad=True, c128=c128)
-    ke = min(B, 4)
+    ke = B
     eref = np.array([separable_energy(ell, inst.c0, xb) for xb in x[:ke]])
     gref = np.array([separable_grad(ell, inst.c0, xb) for xb in x[:ke]])
     tol_e, tol_g = (1e-10, 1e-8) if c128 else (1e-5, 1e-5)
     sigma = pb.info.sigma_c
     assert rel_e(e[:ke], eref, sigma) <= tol_e
-    assert rel_g(g[:ke], gref) <= tol_g  # FD of the closed form is accurate to ~1e-9
+    # FD of the closed form is accurate to ~1e-9; complex64 gradients carry an absolute error of about
+    # 1e-7 sigma_C, so states with a gradient below 1e-2 sigma_C are compared on that scale
+    assert rel_g(g[:ke], gref, 0.0 if c128 else 1e-2 * sigma) <= tol_g
 
 
 @pytest.fixture(scope="module")
@@ -93,8 +115,10 @@ def test_cluster_product_n28_energy_and_gradient(cluster_problem, c128):
     p = 4
     B = 2 if c128 else WAVE
     x = W.random_params(p, B, 44)
+    if not c128:
+        pin_bench_schedule(pb, p)
     e, g = pb.evaluate(x, grad=True, c128=c128)
-    ks = min(B, 3)
+    ks = B
     eref = np.full(ks, inst.c0)
     gref = np.zeros((ks, 2 * p))
     for off, m in inst.meta["blocks"]:
@@ -105,7 +129,7 @@ def test_cluster_product_n28_energy_and_gradient(cluster_problem, c128):
             gref[b] += gb
     tol = 1e-10 if c128 else 1e-5
     assert rel_e(e[:ks], eref, pb.info.sigma_c) <= tol
-    assert rel_g(g[:ks], gref) <= tol
+    assert rel_g(g[:ks], gref, 0.0 if c128 else 1e-2 * pb.info.sigma_c) <= tol
 
 
 def test_workload_n28_complex64_vs_complex128_and_fd():
@@ -113,6 +137,7 @@ def test_workload_n28_complex64_vs_complex128_and_fd():
     kernel, and the complex128 gradient against central differences of complex128 energies."""
     inst, x = W.workload3(batch=WAVE, p=8)
     pb = Problem(inst.H, inst.f, inst.c0)
+    pin_bench_schedule(pb, 8)
     e64, g64 = pb.evaluate(x, grad=True)
     e128, g128 = pb.evaluate(x[:2], grad=True, c128=True)
     sigma = pb.info.sigma_c
