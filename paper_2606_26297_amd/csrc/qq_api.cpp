@@ -62,7 +62,6 @@ struct ProfRec {
     qq_launch_record meta;
 };
 bool g_prof = false;
-bool g_force_generic = false;  // QQ_GENERIC_PASSES=1: use the generic pass kernel everywhere
 std::vector<ProfRec> g_prof_log;
 
 // Event-timed record of one auxiliary launch (cost diagonal, probabilities, top-k, ...) when
@@ -545,7 +544,7 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
     (void)es;
     if (plan.nslots > kMaxSlots) return fail(QQ_E_UNSUPPORTED, "plan needs %d accumulator slots (max %d)", plan.nslots, kMaxSlots);
     // Specialised complex64 kernels serve multi-pass, non-partitioned plans.
-    const bool use_fast = !c128 && plan.sets.size() > 1 && !g_force_generic && pb->n <= kFastMaxN;
+    const bool use_fast = !c128 && plan.sets.size() > 1 && pb->n <= kFastMaxN;
     int slot_base = 0;
     for (const auto &pp : plan.passes) {
         if ((int)pp.ops.size() > kMaxOps) return fail(QQ_E_UNSUPPORTED, "pass has %zu ops (max %d)", pp.ops.size(), kMaxOps);
@@ -1127,7 +1126,6 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
                             qq_problem **out)
 {
     g_err.clear();
-    if (const char *e = std::getenv("QQ_GENERIC_PASSES")) g_force_generic = e[0] == '1';
     if (!out) return fail(QQ_E_INVALID, "out is NULL");
     if (n < 1 || n > QQ_MAX_N) return fail(QQ_E_INVALID, "n = %d outside [1, %d]", n, QQ_MAX_N);
     if (!H) return fail(QQ_E_INVALID, "H is NULL");
