@@ -481,8 +481,8 @@ qq_status qq_sample_stats(qq_problem *prob, int64_t shots, const uint64_t *indic
  *                   include_warm + perturbed_starts + random_starts
  * flags: 0, QQ_C128 and/or QQ_PARTITIONED (as for qq_evaluate).  Allocates its
  * own device memory; synchronises `stream`.
- * Errors: QQ_E_INVALID (options, missing inputs), and those of qq_graph_create
- * and qq_evaluate.
+ * Errors: QQ_E_INVALID (options, missing inputs, non-finite points or offsets),
+ * and those of qq_graph_create and qq_evaluate.
  */
 typedef struct {
     int p_max;            /* depths 1 .. p_max, p_max <= QQ_MAX_P */

@@ -84,6 +84,12 @@ extern "C" qq_status qq_optimize(qq_problem *pb, const qq_optimize_options *o, c
         return fail_msg(QQ_E_INVALID, "flags 0x%x: only QQ_C128 and QQ_PARTITIONED are accepted", o->flags);
     if (!random_points) return fail_msg(QQ_E_INVALID, "random_points is NULL");
     if (P > 0 && pmax >= 2 && !perturbations) return fail_msg(QQ_E_INVALID, "perturbations is NULL");
+    const int64_t nrand = (int64_t)R * pmax * (pmax + 1);
+    const int64_t npert = (P > 0 && pmax >= 2) ? (int64_t)P * (pmax * (pmax + 1) - 2) : 0;
+    for (int64_t i = 0; i < nrand; ++i)
+        if (!std::isfinite(random_points[i])) return fail_msg(QQ_E_INVALID, "random_points has a non-finite value");
+    for (int64_t i = 0; i < npert; ++i)
+        if (!std::isfinite(perturbations[i])) return fail_msg(QQ_E_INVALID, "perturbations has a non-finite value");
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     if (hipSetDevice(problem_device(pb)) != hipSuccess) return fail_msg(QQ_E_DEVICE, "hipSetDevice failed");
 

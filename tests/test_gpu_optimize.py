@@ -105,5 +105,12 @@ def test_search_validation():
         with pytest.raises(N.QQError) as ei:
             N.qq_optimize(pb.handle, dict(base, **bad), rp, pt)
         assert ei.value.status == N.QQ_E_INVALID, bad
+    nan_pts, inf_off = pts.copy(), off.copy()
+    nan_pts[3] = np.nan
+    inf_off[1] = np.inf
+    for rp, pt in ((nan_pts, off), (pts, inf_off)):
+        with pytest.raises(N.QQError) as ei:
+            N.qq_optimize(pb.handle, base, rp, pt)
+        assert ei.value.status == N.QQ_E_INVALID
     with pytest.raises(ValueError):
         N.qq_optimize(pb.handle, base, pts[:-1], off)
