@@ -1,0 +1,78 @@
+"""Writes regular3_n28_p8_oracle.json: the FP64 CPU oracle's energy and adjoint gradient for the
+first two starts of the n = 28, p = 8 3-regular benchmark workload (the instance and angle draws of
+paper_2606_26297_amd.workloads.workload3, seeds 103 / 203).
+
+Calls only the oracle (cost diagonal in canonical order, state by eq. (10)-(13), energy eq. (17),
+adjoint gradient) and the seeded input generators; nothing here touches the GPU library.  The two
+starts run in two forked processes that share the diagonal (about 10 GiB and 10-15 minutes each).
+The file records SHA-256 digests of the instance and of the two angle vectors, so a test can check
+that the generators still draw the same inputs.
+
+    python tests/golden/make_regular3_n28_oracle.py
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2606_26297_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "regular3_n28_p8_oracle.json")
+STARTS = (0, 1)
+_DIAG = None
+
+
+def digest(*arrays) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
+    return h.hexdigest()
+
+
+def one_start(args):
+    b, x = args
+    t0 = time.perf_counter()
+    e, g = O.gradient(_DIAG, x)
+    return b, e, [float(v) for v in g], time.perf_counter() - t0
+
+
+def main():
+    global _DIAG
+    inst, x = W.workload3()
+    t0 = time.perf_counter()
+    _DIAG = O.cost_diagonal(inst.H, inst.f, inst.c0)
+    t_diag = time.perf_counter() - t0
+    with mp.get_context("fork").Pool(len(STARTS)) as pool:
+        res = pool.map(one_start, [(b, x[b]) for b in STARTS])
+    out = {
+        "what": "FP64 CPU oracle: energy J(x) (eq. (17)) and adjoint gradient, interleaved like x",
+        "workload": "regular3_n28_p8 (workloads.workload3: 3-regular graph QUBO, n = 28, seed 103; "
+                    "angles U[0, pi], p = 8, seed 203, batch 64)",
+        "n": inst.n, "p": 8,
+        "instance_sha256": digest(inst.H, inst.f, np.array([inst.c0])),
+        "starts": [
+            {"start": b, "x_sha256": digest(x[b]), "energy": e, "gradient": g, "seconds": round(s, 1)}
+            for b, e, g, s in sorted(res)
+        ],
+        "diagonal_seconds": round(t_diag, 1),
+        "script": "tests/golden/make_regular3_n28_oracle.py",
+    }
+    with open(OUT, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({k: out[k] for k in ("instance_sha256", "diagonal_seconds")}),
+          [(s["start"], s["energy"], s["seconds"]) for s in out["starts"]])
+
+
+if __name__ == "__main__":
+    main()

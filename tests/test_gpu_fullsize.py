@@ -10,11 +10,16 @@ these checks use results that hold at any size:
   * cluster-product instances (couplings only inside blocks of 7 qubits):
     E = c0 + sum_m E_m and grad = sum_m grad_m with each block solved by the oracle.
 The blocks straddle every qubit-set boundary of the n = 28 pass plan
-(sets {0..11}, {12..15, 24..27}, {16..23}).
+(sets {0..11}, {12..15, 24..27}, {16..23}).  The benchmark instance itself is checked against
+the FP64 oracle's energy and adjoint gradient of two starts, computed once on the CPU by
+tests/golden/make_regular3_n28_oracle.py (about 15 minutes) and stored in tests/golden/.
 Tolerance: 1e-5 relative for complex64 (energy |dE| / max(|E|, sigma_C),
 gradient ||dg||_inf / max(||g||_inf, 1e-2 sigma_C)), 1e-10 for complex128 (gradient relative to
 ||g||_inf).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -152,3 +157,19 @@ def test_workload_n28_complex64_vs_complex128_and_fd():
         xm[r, j] -= h
     fd = (pb.evaluate(xp, c128=True) - pb.evaluate(xm, c128=True)) / (2 * h)
     assert np.max(np.abs(fd - g128[0, js])) <= 1e-6 * np.max(np.abs(g128[0]))
+
+
+def test_benchmark_instance_vs_stored_oracle():
+    """The benchmark instance (3-regular, n = 28, p = 8) in the timed configuration against the
+    stored FP64 oracle values of starts 0 and 1 (energy and all 16 partial derivatives)."""
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "regular3_n28_p8_oracle.json")))
+    inst, x = W.workload3(batch=WAVE, p=8)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    pin_bench_schedule(pb, 8)
+    e, g = pb.evaluate(x, grad=True)
+    sigma = pb.info.sigma_c
+    for s in ref["starts"]:
+        b = s["start"]
+        gr = np.array(s["gradient"])
+        assert abs(e[b] - s["energy"]) / max(abs(s["energy"]), sigma) <= 1e-5, (b, e[b], s["energy"])
+        assert np.max(np.abs(g[b] - gr)) <= 1e-5 * max(np.max(np.abs(gr)), 1e-2 * sigma), (b, g[b], gr)
