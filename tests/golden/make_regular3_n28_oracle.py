@@ -4,7 +4,8 @@ paper_2606_26297_amd.workloads.workload3, seeds 103 / 203).
 
 Calls only the oracle (cost diagonal in canonical order, state by eq. (10)-(13), energy eq. (17),
 adjoint gradient) and the seeded input generators; nothing here touches the GPU library.  The two
-starts run in two forked processes that share the diagonal (about 10 GiB and 10-15 minutes each).
+starts run in two forked processes that share the diagonal (about 10 GiB and 19 minutes each,
+after 2 minutes for the diagonal).
 The file records SHA-256 digests of the instance and of the two angle vectors, so a test can check
 that the generators still draw the same inputs.
 

@@ -12,7 +12,7 @@ these checks use results that hold at any size:
 The blocks straddle every qubit-set boundary of the n = 28 pass plan
 (sets {0..11}, {12..15, 24..27}, {16..23}).  The benchmark instance itself is checked against
 the FP64 oracle's energy and adjoint gradient of two starts, computed once on the CPU by
-tests/golden/make_regular3_n28_oracle.py (about 15 minutes) and stored in tests/golden/.
+tests/golden/make_regular3_n28_oracle.py (about 21 minutes) and stored in tests/golden/.
 Tolerance: 1e-5 relative for complex64 (energy |dE| / max(|E|, sigma_C),
 gradient ||dg||_inf / max(||g||_inf, 1e-2 sigma_C)), 1e-10 for complex128 (gradient relative to
 ||g||_inf).
