@@ -195,8 +195,37 @@ def _stream_ptr(stream):
     return int(stream.cuda_stream)
 
 
-def _dev_ptr(t):
-    return ctypes.c_void_p(int(t.data_ptr()))
+_F64 = ("float64",)
+_IDX = ("uint64", "int64")
+_AMP = ("complex64", "complex128", "float32", "float64")
+
+
+def _need(p, batch, per):
+    """Bytes a buffer of `per` doubles per parameter set needs, or 0 when p or batch is out of range
+    (the library then rejects the call with its own error code)."""
+    p, batch = int(p), int(batch)
+    return batch * per(p) * 8 if 1 <= p <= QQ_MAX_P and batch >= 1 else 0
+
+
+def _buf(x, nbytes, name, device, dtypes=None):
+    """Address of a caller buffer after checking it: a contiguous CUDA tensor (device) or a
+    C-contiguous numpy array (host) of an accepted element type holding at least nbytes.  A short or
+    strided buffer would otherwise be read or written out of bounds by the library."""
+    if device:
+        if not getattr(x, "is_cuda", False):
+            raise ValueError(f"{name}: a CUDA tensor is required with the *_ON_DEVICE flag")
+        if not x.is_contiguous():
+            raise ValueError(f"{name}: the tensor must be contiguous")
+        size, dt, addr = x.numel() * x.element_size(), str(x.dtype).replace("torch.", ""), int(x.data_ptr())
+    else:
+        if not isinstance(x, np.ndarray) or not x.flags["C_CONTIGUOUS"]:
+            raise ValueError(f"{name}: a C-contiguous numpy array is required")
+        size, dt, addr = x.nbytes, x.dtype.name, x.ctypes.data
+    if dtypes is not None and dt not in dtypes:
+        raise TypeError(f"{name}: element type {dt}, expected one of {', '.join(dtypes)}")
+    if size < nbytes:
+        raise ValueError(f"{name}: holds {size} bytes, {nbytes} needed")
+    return ctypes.c_void_p(addr)
 
 
 # ---- one wrapper per entry point ------------------------------------------------------------
@@ -249,7 +278,9 @@ def qq_coefficients(handle, n):
 
 def qq_cost_diagonal(handle, out, flags=0, stream=None):
     """out: numpy array (int32 or float64) or a device tensor with QQ_OUT_ON_DEVICE."""
-    ptr = _dev_ptr(out) if flags & QQ_OUT_ON_DEVICE else out.ctypes.data_as(_vp)
+    info = qq_problem_info(handle)
+    ptr = _buf(out, (1 << info.n) * (4 if info.is_integer else 8), "out", flags & QQ_OUT_ON_DEVICE,
+               ("int32",) if info.is_integer else _F64)
     _check(lib().qq_cost_diagonal(handle, ptr, int(flags), _stream_ptr(stream)))
     return out
 
@@ -273,34 +304,33 @@ def qq_workspace_size(handle, p, batch, flags) -> int:
 
 def qq_evaluate(handle, p, batch, params, flags, workspace, ws_bytes, stream, energy_out, grad_out):
     """params / energy_out / grad_out: numpy arrays, or device tensors with the *_ON_DEVICE flags."""
-    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
-    if flags & QQ_OUT_ON_DEVICE:
-        ep = _dev_ptr(energy_out)
-        gp = _dev_ptr(grad_out) if grad_out is not None else None
-    else:
-        ep = energy_out.ctypes.data_as(_vp)
-        gp = grad_out.ctypes.data_as(_vp) if grad_out is not None else None
-    wp = None if workspace is None else _dev_ptr(workspace)
+    pp = _buf(params, _need(p, batch, lambda q: 2 * q), "params", flags & QQ_PARAMS_ON_DEVICE, _F64)
+    ep = _buf(energy_out, _need(p, batch, lambda q: 1), "energy_out", flags & QQ_OUT_ON_DEVICE, _F64)
+    gp = None if grad_out is None else _buf(grad_out, _need(p, batch, lambda q: 2 * q), "grad_out",
+                                            flags & QQ_OUT_ON_DEVICE, _F64)
+    wp = None if workspace is None else _buf(workspace, int(ws_bytes), "workspace", True)
     _check(lib().qq_evaluate(handle, int(p), int(batch), pp, int(flags), wp, int(ws_bytes), _stream_ptr(stream), ep,
                              gp))
 
 
 def qq_state(handle, p, params, flags, psi_out, stream=None):
-    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
-    op = _dev_ptr(psi_out) if flags & QQ_OUT_ON_DEVICE else psi_out.ctypes.data_as(_vp)
+    n = qq_problem_info(handle).n
+    pp = _buf(params, _need(p, 1, lambda q: 2 * q), "params", flags & QQ_PARAMS_ON_DEVICE, _F64)
+    op = _buf(psi_out, (1 << n) * (16 if flags & QQ_C128 else 8), "psi_out", flags & QQ_OUT_ON_DEVICE, _AMP)
     _check(lib().qq_state(handle, int(p), pp, int(flags), op, _stream_ptr(stream)))
     return psi_out
 
 
 def qq_probabilities(handle, p, params, flags, prob_out, stream=None):
-    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
-    op = _dev_ptr(prob_out) if flags & QQ_OUT_ON_DEVICE else prob_out.ctypes.data_as(_vp)
+    n = qq_problem_info(handle).n
+    pp = _buf(params, _need(p, 1, lambda q: 2 * q), "params", flags & QQ_PARAMS_ON_DEVICE, _F64)
+    op = _buf(prob_out, (1 << n) * 8, "prob_out", flags & QQ_OUT_ON_DEVICE, _F64)
     _check(lib().qq_probabilities(handle, int(p), pp, int(flags), op, _stream_ptr(stream)))
     return prob_out
 
 
 def qq_topk(handle, p, params, flags, k, stream=None):
-    pp = _dev_ptr(params) if flags & QQ_PARAMS_ON_DEVICE else params.ctypes.data_as(_vp)
+    pp = _buf(params, _need(p, 1, lambda q: 2 * q), "params", flags & QQ_PARAMS_ON_DEVICE, _F64)
     idx = np.zeros(k, dtype=np.uint64)
     prob = np.zeros(k)
     cost = np.zeros(k)
@@ -347,19 +377,17 @@ def qq_evaluate_many(handles, p, batch, params, flags, opt, workspace, ws_bytes,
     """params[i], energy_out[i], grad_out[i]: numpy arrays, or device tensors with the *_ON_DEVICE flags;
     grad_out may be None without QQ_GRAD."""
     count, hs, pa, ba = _many_arrays(handles, p, batch)
-
-    def ptr(a, dev):
-        return (int(a.data_ptr()) if dev else a.ctypes.data) if a is not None else None
-
     pin = flags & QQ_PARAMS_ON_DEVICE
     pout = flags & QQ_OUT_ON_DEVICE
-    for i in range(count):
-        if not pin and (params[i].dtype != np.float64 or not params[i].flags["C_CONTIGUOUS"]):
-            raise ValueError("params[%d] must be a C-contiguous float64 array" % i)
-    pp = (_vp * count)(*[ptr(params[i], pin) for i in range(count)])
-    ep = (_vp * count)(*[ptr(energy_out[i], pout) for i in range(count)])
-    gp = (_vp * count)(*[ptr(grad_out[i], pout) if grad_out is not None else None for i in range(count)])
-    wp = None if workspace is None else _dev_ptr(workspace)
+    if len(params) != count or len(energy_out) != count or (grad_out is not None and len(grad_out) != count):
+        raise ValueError("params, energy_out and grad_out need one entry per problem")
+    sizes = [_need(pa[i], ba[i], lambda q: 2 * q) for i in range(count)]
+    pp = (_vp * count)(*[_buf(params[i], sizes[i], f"params[{i}]", pin, _F64).value for i in range(count)])
+    ep = (_vp * count)(*[_buf(energy_out[i], _need(pa[i], ba[i], lambda q: 1), f"energy_out[{i}]", pout, _F64).value
+                         for i in range(count)])
+    gp = (_vp * count)(*[_buf(grad_out[i], sizes[i], f"grad_out[{i}]", pout, _F64).value
+                         if grad_out is not None else None for i in range(count)])
+    wp = None if workspace is None else _buf(workspace, int(ws_bytes), "workspace", True)
     _check(lib().qq_evaluate_many(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
                                   ctypes.cast(pp, _vp), int(flags), _many_options(opt), wp, int(ws_bytes),
                                   _stream_ptr(stream), ctypes.cast(ep, _vp),
@@ -375,7 +403,8 @@ def qq_graph_create(handle, p, batch, flags, adam, params, history=0, stream=Non
             raise ValueError("adam = (lr, beta1, beta2, eps)")
         hp = _ptr(a)
     out = _vp()
-    _check(lib().qq_graph_create(handle, int(p), int(batch), int(flags), hp, _dev_ptr(params), int(history),
+    xp = _buf(params, _need(p, batch, lambda q: 2 * q), "params", True, _F64)
+    _check(lib().qq_graph_create(handle, int(p), int(batch), int(flags), hp, xp, int(history),
                                  _stream_ptr(stream), ctypes.byref(out)))
     return out
 
@@ -412,14 +441,15 @@ def qq_sample(handle, p, params, uniforms, flags=0, stream=None, out=None):
     """Shots from the exact distribution: basis indices (uint64) for the given uniforms in [0, 1).
     Host numpy inputs, or torch device tensors with QQ_PARAMS_ON_DEVICE (params and uniforms) and
     QQ_OUT_ON_DEVICE (out, a device uint64/int64 tensor of the shot count)."""
-    if flags & QQ_PARAMS_ON_DEVICE:
-        pp, up, shots = _dev_ptr(params), _dev_ptr(uniforms), int(uniforms.numel())
-    else:
+    dev_in = flags & QQ_PARAMS_ON_DEVICE
+    if not dev_in:
         params = np.ascontiguousarray(params, dtype=np.float64).ravel()
         uniforms = np.ascontiguousarray(uniforms, dtype=np.float64).ravel()
-        pp, up, shots = params.ctypes.data_as(_vp), uniforms.ctypes.data_as(_vp), int(uniforms.size)
+    shots = int(uniforms.numel()) if hasattr(uniforms, "numel") else int(np.size(uniforms))
+    pp = _buf(params, _need(p, 1, lambda q: 2 * q), "params", dev_in, _F64)
+    up = _buf(uniforms, shots * 8, "uniforms", dev_in, _F64)
     if flags & QQ_OUT_ON_DEVICE:
-        op = _dev_ptr(out)
+        op = _buf(out, shots * 8, "out", True, _IDX)
     else:
         out = np.empty(shots, dtype=np.uint64)
         op = out.ctypes.data_as(_vp)
