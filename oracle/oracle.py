@@ -114,6 +114,23 @@ def cost_diagonal_real(ell, b, c0):
     return out
 
 
+def cost_at_real(ell, b, c0, z):
+    """C(z) of eq. (6) for one basis index z, real coefficients, FP64 in the canonical order: c0,
+    then l_i over the set bits in ascending i, then b_ij over the set pairs row by row (the order of
+    cost_diagonal_real, one index at a time, so full-size diagonals can be checked at sampled z)."""
+    n = len(ell)
+    acc = float(c0)
+    for i in range(n):
+        if (z >> i) & 1:
+            acc += float(ell[i])
+    for i in range(n):
+        if (z >> i) & 1:
+            for j in range(i + 1, n):
+                if (z >> j) & 1:
+                    acc += float(b[i][j])
+    return acc
+
+
 # --- Ising / Pauli form (eq. (7)-(9)) -------------------------------------------------------
 
 def ising_coefficients(ell, b, c0):

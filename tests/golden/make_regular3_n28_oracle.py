@@ -4,10 +4,12 @@ paper_2606_26297_amd.workloads.workload3, seeds 103 / 203).
 
 Calls only the oracle (cost diagonal in canonical order, state by eq. (10)-(13), energy eq. (17),
 adjoint gradient) and the seeded input generators; nothing here touches the GPU library.  The two
-starts run in two forked processes that share the diagonal (about 10 GiB and 19 minutes each,
+starts run in two forked processes that share the diagonal (about 10 GiB and 16-19 minutes each,
 after 2 minutes for the diagonal).
 The file records SHA-256 digests of the instance and of the two angle vectors, so a test can check
-that the generators still draw the same inputs.
+that the generators still draw the same inputs, and the SHA-256 of the oracle's FP64 cost diagonal
+(2^28 entries in canonical summation order), against which the library's diagonal is checked bit
+for bit.
 
     python tests/golden/make_regular3_n28_oracle.py
 """
@@ -61,6 +63,7 @@ def main():
                     "angles U[0, pi], p = 8, seed 203, batch 64)",
         "n": inst.n, "p": 8,
         "instance_sha256": digest(inst.H, inst.f, np.array([inst.c0])),
+        "diagonal_sha256": hashlib.sha256(np.ascontiguousarray(_DIAG, dtype=np.float64).data).hexdigest(),
         "starts": [
             {"start": b, "x_sha256": digest(x[b]), "energy": e, "gradient": g, "seconds": round(s, 1)}
             for b, e, g, s in sorted(res)

@@ -32,6 +32,7 @@ def test_stored_oracle_values_match_the_generators():
     inst, x = W.workload3()
     assert ref["n"] == inst.n == 28 and ref["p"] == 8
     assert ref["instance_sha256"] == digest(inst.H, inst.f, np.array([inst.c0]))
+    assert len(ref["diagonal_sha256"]) == 64 and int(ref["diagonal_sha256"], 16) >= 0
     ell, b = O.canonicalise(inst.H, inst.f)
     bound = abs(inst.c0) + np.sum(np.abs(ell)) + np.sum(np.abs(b))
     assert [s["start"] for s in ref["starts"]] == [0, 1]

@@ -12,7 +12,8 @@ these checks use results that hold at any size:
 The blocks straddle every qubit-set boundary of the n = 28 pass plan
 (sets {0..11}, {12..15, 24..27}, {16..23}).  The benchmark instance itself is checked against
 the FP64 oracle's energy and adjoint gradient of two starts, computed once on the CPU by
-tests/golden/make_regular3_n28_oracle.py (about 21 minutes) and stored in tests/golden/.
+tests/golden/make_regular3_n28_oracle.py (about 20 minutes) and stored in tests/golden/, and its
+cost diagonal against the oracle's bit for bit (stored SHA-256, sampled one-index sums).
 Tolerance: 1e-5 relative for complex64 (energy |dE| / max(|E|, sigma_C),
 gradient ||dg||_inf / max(||g||_inf, 1e-2 sigma_C)), 1e-10 for complex128 (gradient relative to
 ||g||_inf).
@@ -173,3 +174,20 @@ def test_benchmark_instance_vs_stored_oracle():
         gr = np.array(s["gradient"])
         assert abs(e[b] - s["energy"]) / max(abs(s["energy"]), sigma) <= 1e-5, (b, e[b], s["energy"])
         assert np.max(np.abs(g[b] - gr)) <= 1e-5 * max(np.max(np.abs(gr)), 1e-2 * sigma), (b, g[b], gr)
+
+
+def test_benchmark_cost_diagonal_bit_exact():
+    """The library's FP64 cost diagonal of the benchmark instance (2^28 entries, canonical summation
+    order) equals the oracle's bit for bit: its SHA-256 against the stored one, and 2000 sampled
+    entries against the oracle's one-index sum."""
+    import hashlib
+
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "regular3_n28_p8_oracle.json")))
+    inst, _ = W.workload3(batch=1)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    d = pb.diagonal()
+    assert d.dtype == np.float64 and d.size == 1 << N
+    assert hashlib.sha256(d.data).hexdigest() == ref["diagonal_sha256"]
+    ell, b = O.canonicalise(inst.H, inst.f)
+    zs = np.random.default_rng(72).integers(0, 1 << N, size=2000)
+    assert all(d[z] == O.cost_at_real(ell, b, inst.c0, int(z)) for z in zs)

@@ -69,6 +69,22 @@ def test_diag_real_vs_bruteforce():
         assert np.max(np.abs(d - ref)) <= 1e-13 * scale
 
 
+def test_cost_at_one_index_equals_the_diagonal_exactly():
+    # the one-index form sums in the same canonical order, so it reproduces every FP64 entry; and
+    # both agree with the brute-force z^T H z + f.z + c0 within rounding
+    rng = np.random.default_rng(110)
+    n = 9
+    H = rng.normal(size=(n, n))
+    f = rng.normal(size=n)
+    c0 = float(rng.normal())
+    ell, b = O.canonicalise(H, f)
+    d = O.cost_diagonal_real(ell, b, c0)
+    one = np.array([O.cost_at_real(ell, b, c0, z) for z in range(1 << n)])
+    assert np.array_equal(one, d)
+    ref = brute_force_F(H, f, c0)
+    assert np.max(np.abs(one - ref)) <= 1e-13 * (abs(c0) + np.abs(H).sum() + np.abs(f).sum())
+
+
 def test_real_path_equals_integer_path_on_integer_data():
     inst, _ = W.workload1()
     ell, b = O.canonicalise(inst.H, inst.f)
