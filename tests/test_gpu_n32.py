@@ -9,7 +9,8 @@ any size (1e-5 relative; energy |dE| / max(|E|, sigma_C), gradient
   * the dense N(0,1) multi-QPU workload (496 couplings, 4 QPUs of 8 variables,
     contiguous allocation, p = 2, two parameter sets): the partitioned energy,
     gradient and final state against the monolithic ones (the state compared on
-    the device, ||psi_part - psi_mono||_2 <= 1e-5).
+    the device, ||psi_part - psi_mono||_2 <= 1e-5), and the complex64 energy and
+    gradient against the complex128 generic kernel.
 Device memory: the diagonal and the cross diagonal (FP64, 32 GiB each) plus the
 states of the evaluation; at most about 160 GiB at once.
 """
@@ -101,5 +102,24 @@ def test_n32_multi_qpu_workload_partitioned_equals_monolithic():
         del psi0, psi1
         torch.cuda.empty_cache()
         assert abs(norm - 1.0) <= 1e-5 and diff <= 1e-5, (norm, diff)
+    finally:
+        pb.close()
+
+
+def test_n32_multi_qpu_workload_complex64_vs_complex128():
+    """The same instance, first parameter set, monolithic: the complex64 specialised kernels
+    (including the 64-bit-offset instances of the last, partial high set) against the complex128
+    generic kernel, energy and gradient at 1e-5 (gradient on the scale max(||g||_inf, 1e-2 sigma_C)).
+    complex128 at n = 32 holds 64 GiB per state: 128 GiB for psi and lambda plus the 32 GiB diagonal."""
+    inst, x, _ = W.workload5()
+    pb = Problem(inst.H, inst.f, inst.c0)
+    try:
+        sig = pb.info.sigma_c
+        print("complex64", flush=True)
+        e64, g64 = pb.evaluate(x[:1], grad=True)
+        print("complex128", flush=True)
+        e128, g128 = pb.evaluate(x[:1], grad=True, c128=True)
+        assert e_rel(e64, e128, sig) <= 1e-5, (e64, e128)
+        assert np.max(np.abs(g64 - g128)) <= 1e-5 * max(np.max(np.abs(g128)), 1e-2 * sig), (g64, g128)
     finally:
         pb.close()
