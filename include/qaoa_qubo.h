@@ -229,6 +229,58 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
                            size_t ws_bytes, void *stream, double *const *energy_out, double *const *grad_out);
 
 /*
+ * Evaluation with every gradient held to a relative tolerance (the error
+ * against exact arithmetic stated per result).  Same objective and gradient
+ * as qq_evaluate / qq_evaluate_many (eq. (17), adjoint derivatives in the
+ * layout of x).
+ *
+ * Complex64 states carry rounding errors that do not shrink with the
+ * gradient: on a parameter set where dJ/dx is small next to the spread of
+ * C (sigma_C, eq. (9)), ||dg||_inf / ||g||_inf can exceed any fixed
+ * tolerance.  These calls first evaluate in complex64, then bound each
+ * set's gradient error by the complex64 error model
+ *     ||dg||_inf <= QQ_GUARD_REL * ||g||_inf
+ *                   + QQ_GUARD_K * 2^-24 * sigma_C^2 * 2^(-n/2)
+ * (a relative part from coefficient and phase roundings, and the random
+ * part of the rounding of 2^n stored amplitudes in the gamma-derivative
+ * sums, each term of which carries (C - alpha)^2), and recompute with
+ * complex128 states every set whose bound exceeds tol * ||g||_inf.  The
+ * constants come from measurements against the FP64 oracle (the uneven
+ * batch of 512 problems, n = 10..22, p = 1..6) and the complex128 path
+ * (n = 28, p = 8, 64 sets; n = 32), with margin over the largest ratio seen.
+ * Energies need no recomputation: their complex64 error stays below about
+ * 1e-6 of max(|J|, sigma_C).
+ *
+ *   tol           relative gradient tolerance; 0 selects 1e-5
+ *   flags         QQ_ENERGY / QQ_GRAD / QQ_PARTITIONED / QQ_C128 (host
+ *                 params and outputs only; without QQ_GRAD nothing is
+ *                 recomputed; with QQ_C128 every set is complex128)
+ *   c128_out      batch int32 (may be NULL): 1 where the returned result was
+ *                 computed with complex128 states
+ *   grad_err_out  batch doubles (may be NULL): the bound on ||dg||_inf of
+ *                 the returned gradient (complex64 sets: the model above;
+ *                 complex128 sets: 1e-10 * ||g||_inf); 0 without QQ_GRAD
+ * The library allocates the workspaces of both passes for the call.
+ * Errors: those of qq_evaluate (qq_evaluate_many), and QQ_E_UNSUPPORTED for
+ * QQ_PARAMS_ON_DEVICE / QQ_OUT_ON_DEVICE.
+ */
+#define QQ_GUARD_REL 4e-6
+#define QQ_GUARD_K 40.0
+
+qq_status qq_evaluate_guarded(qq_problem *prob, int p, int batch, const double *params, int flags, double tol,
+                              void *stream, double *energy_out, double *grad_out, int32_t *c128_out,
+                              double *grad_err_out);
+
+/* The same for many problems: complex64 through one persistent launch (qq_evaluate_many), then the
+ * sets whose bound exceeds the tolerance through qq_evaluate with complex128 states, problem by
+ * problem.  c128_out[i] and grad_err_out[i] (each array may be NULL, or hold NULL entries) have
+ * batch[i] entries.  QQ_C128 and QQ_PARTITIONED are not accepted (as for qq_evaluate_many). */
+qq_status qq_evaluate_many_guarded(int count, qq_problem *const *problems, const int *p, const int *batch,
+                                   const double *const *params, int flags, const qq_many_options *opt, double tol,
+                                   void *stream, double *const *energy_out, double *const *grad_out,
+                                   int32_t *const *c128_out, double *const *grad_err_out);
+
+/*
  * Schedules and the autotuner (circuit-reuse section: work prepared once per
  * problem and settings and reused; here the launch schedule).
  *

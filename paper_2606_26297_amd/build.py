@@ -16,7 +16,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["qq_kernels.hip", "qq_fast.hip", "qq_many.hip", "qq_optim.hip", "qq_plain.hip", "qq_sample.hip", "qq_telegate.hip"]
+HIP_SOURCES = ["qq_kernels.hip", "qq_fast.hip", "qq_many.hip", "qq_optim.hip", "qq_plain.hip", "qq_sample.hip",
+               "qq_telegate.hip"]
 CPP_SOURCES = ["qq_api.cpp", "qq_driver.cpp", "qq_alloc.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

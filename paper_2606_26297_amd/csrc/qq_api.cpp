@@ -1978,6 +1978,147 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
     return QQ_OK;
 }
 
+namespace {
+
+// Bound on ||dg||_inf of a complex64 gradient (see qq_evaluate_guarded in the header): a part relative
+// to the gradient, and the random part of the rounding of 2^n stored amplitudes in sums whose terms
+// carry (C - alpha)^2, which grows as 2^(-n/2) of sigma_C^2 per unit rounding.
+double c64_grad_bound(int n, double sigma_c, double gmax)
+{
+    return QQ_GUARD_REL * gmax + QQ_GUARD_K * std::ldexp(sigma_c * sigma_c, -24) * std::pow(2.0, -0.5 * n);
+}
+
+constexpr double kC128GradRel = 1e-10;
+
+double max_abs(const double *g, int m)
+{
+    double r = 0.0;
+    for (int j = 0; j < m; ++j) r = std::max(r, std::fabs(g[j]));
+    return r;
+}
+
+// Recompute the flagged parameter sets of one problem with complex128 states (host in, host out).
+qq_status recompute_c128(qq_problem *pb, int p, const double *params, const std::vector<int> &sets, int flags,
+                         void *stream, double *energy, double *grad)
+{
+    if (sets.empty()) return QQ_OK;
+    const int m = (int)sets.size(), w = 2 * p;
+    std::vector<double> x((size_t)m * w), e(m), g((size_t)m * w);
+    for (int i = 0; i < m; ++i) std::memcpy(&x[(size_t)i * w], params + (size_t)sets[i] * w, w * sizeof(double));
+    const int f = (flags & (QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED)) | QQ_C128;
+    if (qq_status st = qq_evaluate(pb, p, m, x.data(), f, nullptr, 0, stream, e.data(), g.data()); st != QQ_OK)
+        return st;
+    for (int i = 0; i < m; ++i) {
+        energy[sets[i]] = e[i];
+        std::memcpy(grad + (size_t)sets[i] * w, &g[(size_t)i * w], w * sizeof(double));
+    }
+    return QQ_OK;
+}
+
+// Decide, for the complex64 results of one problem, which sets to recompute; fill the outputs.
+std::vector<int> guard_sets(const qq_problem *pb, int p, int batch, const double *grad, double tol, bool c128_all,
+                            int32_t *c128_out, double *err_out)
+{
+    std::vector<int> sets;
+    for (int b = 0; b < batch; ++b) {
+        const double gmax = grad ? max_abs(grad + (size_t)b * 2 * p, 2 * p) : 0.0;
+        bool up = c128_all;
+        double err = 0.0;
+        if (grad && !c128_all) {
+            err = c64_grad_bound(pb->n, pb->sigma_c, gmax);
+            up = err > tol * gmax;
+        }
+        if (up && grad && !c128_all) sets.push_back(b);
+        if (c128_out) c128_out[b] = up ? 1 : 0;
+        if (err_out) err_out[b] = grad ? (up ? kC128GradRel * gmax : err) : 0.0;
+    }
+    return sets;
+}
+
+}  // namespace
+
+qq_status qq_evaluate_guarded(qq_problem *pb, int p, int batch, const double *params, int flags, double tol,
+                              void *stream, double *energy_out, double *grad_out, int32_t *c128_out,
+                              double *grad_err_out)
+{
+    g_err.clear();
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    if (flags & (QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE))
+        return fail(QQ_E_UNSUPPORTED, "qq_evaluate_guarded takes host parameters and outputs");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(QQ_E_INVALID, "tol must be finite and >= 0");
+    if (tol == 0.0) tol = 1e-5;
+    if (!params || !energy_out) return fail(QQ_E_INVALID, "params / energy_out is NULL");
+    const bool grad = flags & QQ_GRAD;
+    if (grad && !grad_out) return fail(QQ_E_INVALID, "QQ_GRAD requires grad_out");
+    // first pass in the requested precision (complex64 unless QQ_C128), into local buffers so that
+    // nothing is written to the caller's outputs on error
+    std::vector<double> e(batch), g(grad ? (size_t)batch * 2 * p : 0);
+    if (qq_status st = qq_evaluate(pb, p, batch, params, flags, nullptr, 0, stream, e.data(), grad ? g.data() : nullptr);
+        st != QQ_OK)
+        return st;
+    std::vector<int32_t> up(batch);
+    std::vector<double> err(batch);
+    const std::vector<int> sets =
+        guard_sets(pb, p, batch, grad ? g.data() : nullptr, tol, (flags & QQ_C128) != 0, up.data(), err.data());
+    if (qq_status st = recompute_c128(pb, p, params, sets, flags, stream, e.data(), g.data()); st != QQ_OK) return st;
+    if (grad)
+        for (int b : sets) err[b] = kC128GradRel * max_abs(&g[(size_t)b * 2 * p], 2 * p);
+    std::memcpy(energy_out, e.data(), batch * sizeof(double));
+    if (grad) std::memcpy(grad_out, g.data(), g.size() * sizeof(double));
+    if (c128_out) std::memcpy(c128_out, up.data(), batch * sizeof(int32_t));
+    if (grad_err_out) std::memcpy(grad_err_out, err.data(), batch * sizeof(double));
+    return QQ_OK;
+}
+
+qq_status qq_evaluate_many_guarded(int count, qq_problem *const *problems, const int *p, const int *batch,
+                                   const double *const *params, int flags, const qq_many_options *opt, double tol,
+                                   void *stream, double *const *energy_out, double *const *grad_out,
+                                   int32_t *const *c128_out, double *const *grad_err_out)
+{
+    g_err.clear();
+    if (qq_status st = validate_many(count, problems, p, batch, flags); st != QQ_OK) return st;
+    if (flags & (QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE))
+        return fail(QQ_E_UNSUPPORTED, "qq_evaluate_many_guarded takes host parameters and outputs");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(QQ_E_INVALID, "tol must be finite and >= 0");
+    if (tol == 0.0) tol = 1e-5;
+    const bool grad = flags & QQ_GRAD;
+    if (!params || !energy_out || (grad && !grad_out)) return fail(QQ_E_INVALID, "params / energy_out / grad_out is NULL");
+    for (int i = 0; i < count; ++i)
+        if (!energy_out[i] || (grad && !grad_out[i])) return fail(QQ_E_INVALID, "output %d is NULL", i);
+    std::vector<std::vector<double>> e(count), g(count);
+    std::vector<double *> ep(count), gp(count);
+    for (int i = 0; i < count; ++i) {
+        e[i].resize(batch[i]);
+        g[i].resize(grad ? (size_t)batch[i] * 2 * p[i] : 1);
+        ep[i] = e[i].data();
+        gp[i] = g[i].data();
+    }
+    if (qq_status st = qq_evaluate_many(count, problems, p, batch, params, flags, opt, nullptr, 0, stream, ep.data(),
+                                        grad ? gp.data() : nullptr);
+        st != QQ_OK)
+        return st;
+    std::vector<std::vector<int32_t>> up(count);
+    std::vector<std::vector<double>> err(count);
+    for (int i = 0; i < count; ++i) {
+        up[i].resize(batch[i]);
+        err[i].resize(batch[i]);
+        const std::vector<int> sets =
+            guard_sets(problems[i], p[i], batch[i], grad ? g[i].data() : nullptr, tol, false, up[i].data(), err[i].data());
+        if (qq_status st = recompute_c128(problems[i], p[i], params[i], sets, flags, stream, e[i].data(), g[i].data());
+            st != QQ_OK)
+            return st;
+        if (grad)
+            for (int b : sets) err[i][b] = kC128GradRel * max_abs(&g[i][(size_t)b * 2 * p[i]], 2 * p[i]);
+    }
+    for (int i = 0; i < count; ++i) {
+        std::memcpy(energy_out[i], e[i].data(), batch[i] * sizeof(double));
+        if (grad) std::memcpy(grad_out[i], g[i].data(), (size_t)batch[i] * 2 * p[i] * sizeof(double));
+        if (c128_out && c128_out[i]) std::memcpy(c128_out[i], up[i].data(), batch[i] * sizeof(int32_t));
+        if (grad_err_out && grad_err_out[i]) std::memcpy(grad_err_out[i], err[i].data(), batch[i] * sizeof(double));
+    }
+    return QQ_OK;
+}
+
 qq_status qq_graph_create(qq_problem *pb, int p, int batch, int flags, const double *adam, double *params,
                           int history, void *stream_, qq_graph **out)
 {

@@ -35,6 +35,9 @@ QQ_C128 = 8
 QQ_PARAMS_ON_DEVICE = 16
 QQ_OUT_ON_DEVICE = 32
 
+QQ_GUARD_REL = 4e-6
+QQ_GUARD_K = 40.0
+
 QQ_MAX_N = 34
 QQ_MAX_P = 64
 QQ_MAX_QPUS = 16
@@ -117,6 +120,9 @@ SIGNATURES = {
     "qq_probabilities": ([_vp, _int, _vp, _int, _vp, _vp], _int),
     "qq_topk": ([_vp, _int, _vp, _int, _int, _u64p, _dp, _dp, _vp], _int),
     "qq_evaluate_plain": ([_vp, _int, _dp, _int, _vp, _dp, _dp], _int),
+    "qq_evaluate_guarded": ([_vp, _int, _int, _vp, _int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp], _int),
+    "qq_evaluate_many_guarded": ([_int, _vp, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), ctypes.c_double,
+                                  _vp, _vp, _vp, _vp, _vp], _int),
     "qq_workspace_size_many": ([_int, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), _szp], _int),
     "qq_evaluate_many": ([_int, _vp, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), _vp, ctypes.c_size_t, _vp,
                           _vp, _vp], _int),
@@ -345,6 +351,45 @@ def qq_evaluate_plain(handle, p, params, flags, stream=None):
     g = np.zeros(2 * p)
     _check(lib().qq_evaluate_plain(handle, int(p), _ptr(x), int(flags), _stream_ptr(stream), _ptr(e), _ptr(g)))
     return float(e[0]), g
+
+
+def qq_evaluate_guarded(handle, p, batch, params, flags, tol, energy_out, grad_out, c128_out=None,
+                        grad_err_out=None, stream=None):
+    """Host numpy arrays only: params [batch, 2p], energy_out [batch], grad_out [batch, 2p] (None without
+    QQ_GRAD), c128_out int32 [batch] and grad_err_out [batch] (each may be None)."""
+    pp = _buf(params, _need(p, batch, lambda q: 2 * q), "params", False, _F64)
+    ep = _buf(energy_out, _need(p, batch, lambda q: 1), "energy_out", False, _F64)
+    gp = None if grad_out is None else _buf(grad_out, _need(p, batch, lambda q: 2 * q), "grad_out", False, _F64)
+    cp = None if c128_out is None else _buf(c128_out, 4 * max(int(batch), 0), "c128_out", False, ("int32",))
+    rp = None if grad_err_out is None else _buf(grad_err_out, _need(p, batch, lambda q: 1), "grad_err_out", False,
+                                                _F64)
+    _check(lib().qq_evaluate_guarded(handle, int(p), int(batch), pp, int(flags), float(tol), _stream_ptr(stream), ep,
+                                     gp, cp, rp))
+
+
+def qq_evaluate_many_guarded(handles, p, batch, params, flags, opt, tol, energy_out, grad_out, c128_out=None,
+                             grad_err_out=None, stream=None):
+    """Host numpy arrays only, one per problem (grad_out None without QQ_GRAD; c128_out int32 and
+    grad_err_out float64 lists may be None)."""
+    count, hs, pa, ba = _many_arrays(handles, p, batch)
+    if len(params) != count or len(energy_out) != count or (grad_out is not None and len(grad_out) != count):
+        raise ValueError("params, energy_out and grad_out need one entry per problem")
+    sizes = [_need(pa[i], ba[i], lambda q: 2 * q) for i in range(count)]
+    ones = [_need(pa[i], ba[i], lambda q: 1) for i in range(count)]
+    pp = (_vp * count)(*[_buf(params[i], sizes[i], f"params[{i}]", False, _F64).value for i in range(count)])
+    ep = (_vp * count)(*[_buf(energy_out[i], ones[i], f"energy_out[{i}]", False, _F64).value for i in range(count)])
+    gp = None if grad_out is None else (_vp * count)(
+        *[_buf(grad_out[i], sizes[i], f"grad_out[{i}]", False, _F64).value for i in range(count)])
+    cp = None if c128_out is None else (_vp * count)(
+        *[_buf(c128_out[i], 4 * int(ba[i]), f"c128_out[{i}]", False, ("int32",)).value for i in range(count)])
+    rp = None if grad_err_out is None else (_vp * count)(
+        *[_buf(grad_err_out[i], ones[i], f"grad_err_out[{i}]", False, _F64).value for i in range(count)])
+    _check(lib().qq_evaluate_many_guarded(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
+                                          ctypes.cast(pp, _vp), int(flags), _many_options(opt), float(tol),
+                                          _stream_ptr(stream), ctypes.cast(ep, _vp),
+                                          None if gp is None else ctypes.cast(gp, _vp),
+                                          None if cp is None else ctypes.cast(cp, _vp),
+                                          None if rp is None else ctypes.cast(rp, _vp)))
 
 
 def _many_options(opt):

@@ -108,6 +108,18 @@ class Problem:
         N.qq_evaluate(self.handle, p, B, x, flags, None, 0, None, e, g)
         return (e, g) if grad else e
 
+    def evaluate_guarded(self, params, tol=1e-5, partitioned=False):
+        """Energies and gradients (host numpy) with every gradient held to `tol` relative: complex64 first,
+        the sets whose complex64 error bound exceeds the tolerance again with complex128 states.
+        Returns (energies, gradients, c128 flags, gradient error bounds)."""
+        x = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+        B, twop = x.shape
+        e, g = np.empty(B), np.empty((B, twop))
+        up, err = np.empty(B, dtype=np.int32), np.empty(B)
+        flags = N.QQ_ENERGY | N.QQ_GRAD | (N.QQ_PARTITIONED if partitioned else 0)
+        N.qq_evaluate_guarded(self.handle, twop // 2, B, x, flags, tol, e, g, up, err)
+        return e, g, up, err
+
     def state(self, params, c128=False, partitioned=False):
         x = np.ascontiguousarray(params, dtype=np.float64).ravel()
         p = x.shape[0] // 2
@@ -161,6 +173,20 @@ def evaluate_many(problems, params, grad=False, options=None, workspace=None):
         stream = torch.cuda.current_stream(device)
     N.qq_evaluate_many(handles, ps, bs, xs, flags, options, ws, ws_bytes, stream, e, g)
     return e, g
+
+
+def evaluate_many_guarded(problems, params, tol=1e-5, options=None):
+    """Energies and gradients of many problems (host numpy lists) with every gradient held to `tol`
+    relative: one complex64 persistent launch, then complex128 for the sets whose bound exceeds the
+    tolerance.  Returns (energies, gradients, c128 flags, gradient error bounds), each a list."""
+    xs = [np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64) for x in params]
+    e = [np.empty(x.shape[0]) for x in xs]
+    g = [np.empty(x.shape) for x in xs]
+    up = [np.empty(x.shape[0], dtype=np.int32) for x in xs]
+    err = [np.empty(x.shape[0]) for x in xs]
+    N.qq_evaluate_many_guarded([pb.handle for pb in problems], [x.shape[1] // 2 for x in xs], [x.shape[0] for x in xs],
+                               xs, N.QQ_ENERGY | N.QQ_GRAD, options, tol, e, g, up, err)
+    return e, g, up, err
 
 
 def _make_autograd():

@@ -11,7 +11,13 @@ that the generators still draw the same inputs, and the SHA-256 of the oracle's 
 (2^28 entries in canonical summation order), against which the library's diagonal is checked bit
 for bit.
 
-    python tests/golden/make_regular3_n28_oracle.py
+With --topk the script adds, to an existing file, the oracle's 12 most probable basis indices of
+start 0 with their probabilities |psi(z)|^2 (decoding section: the elite list; ordered by decreasing
+probability, ties to the lower index), from one forward evaluation of eq. (11) (about 7 minutes on
+one core, diagonal included).  Twelve are stored so that a test of the top 10 can see the gap after
+the tenth.
+
+    python tests/golden/make_regular3_n28_oracle.py [--topk]
 """
 from __future__ import annotations
 
@@ -49,8 +55,30 @@ def one_start(args):
     return b, e, [float(v) for v in g], time.perf_counter() - t0
 
 
+def add_topk(k=12):
+    with open(OUT) as fh:
+        out = json.load(fh)
+    inst, x = W.workload3()
+    t0 = time.perf_counter()
+    d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+    psi = O.qaoa_state(d, x[0])
+    P = O.probabilities(psi)
+    del psi
+    idx = O.topk(P, k)
+    out["top12_start0"] = {"index": [int(v) for v in idx], "probability": [float(P[v]) for v in idx],
+                           "cost": [float(d[v]) for v in idx], "probability_sum": float(np.sum(P)),
+                           "seconds": round(time.perf_counter() - t0, 1)}
+    with open(OUT, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(out["top12_start0"])
+
+
 def main():
     global _DIAG
+    if "--topk" in sys.argv:
+        add_topk()
+        return
     inst, x = W.workload3()
     t0 = time.perf_counter()
     _DIAG = O.cost_diagonal(inst.H, inst.f, inst.c0)

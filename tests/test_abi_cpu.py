@@ -73,3 +73,22 @@ def test_null_arguments_are_rejected(L):
     assert L.qq_evaluate(None, 1, 1, None, 1, None, 0, None, None, None) == N.QQ_E_INVALID
     assert L.qq_set_allocation(None, 2, None, None, None, None) == N.QQ_E_INVALID
     assert N.qq_last_error()
+
+
+def test_guarded_calls_reject_bad_arguments_before_device_work(L):
+    dp = ctypes.POINTER(ctypes.c_double)
+    x = np.array([0.1, 0.2])
+    e = np.zeros(1)
+    assert L.qq_evaluate_guarded(None, 1, 1, x.ctypes.data_as(dp), N.QQ_ENERGY | N.QQ_GRAD, 1e-5, None,
+                                 e.ctypes.data_as(dp), None, None, None) == N.QQ_E_INVALID
+    assert "NULL" in N.qq_last_error()
+    assert L.qq_evaluate_many_guarded(0, None, None, None, None, N.QQ_ENERGY, None, 1e-5, None, None, None, None,
+                                      None) == N.QQ_E_INVALID
+
+
+def test_guard_constants_match_the_header():
+    import re
+
+    text = open(N.HEADER).read()
+    assert float(re.search(r"#define QQ_GUARD_REL (\S+)", text).group(1)) == N.QQ_GUARD_REL
+    assert float(re.search(r"#define QQ_GUARD_K (\S+)", text).group(1)) == N.QQ_GUARD_K

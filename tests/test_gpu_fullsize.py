@@ -14,9 +14,11 @@ The blocks straddle every qubit-set boundary of the n = 28 pass plan
 the FP64 oracle's energy and adjoint gradient of two starts, computed once on the CPU by
 tests/golden/make_regular3_n28_oracle.py (about 20 minutes) and stored in tests/golden/, and its
 cost diagonal against the oracle's bit for bit (stored SHA-256, sampled one-index sums).
-Tolerance: 1e-5 relative for complex64 (energy |dE| / max(|E|, sigma_C),
-gradient ||dg||_inf / max(||g||_inf, 1e-2 sigma_C)), 1e-10 for complex128 (gradient relative to
-||g||_inf).
+All 64 timed starts of the benchmark instance are compared with the complex128 path (itself
+within 1e-11 of the stored oracle values), and the 10 most probable basis indices of start 0 with
+the oracle's (stored, with their probabilities).
+Tolerance: 1e-5 relative for complex64 (energy |dE| / max(|E|, sigma_C), gradient
+||dg||_inf / ||g||_inf, no floor), 1e-10 for complex128.
 """
 import json
 import os
@@ -75,9 +77,9 @@ def rel_e(e, eref, sigma):
     return np.max(np.abs(e - eref) / np.maximum(np.abs(eref), sigma))
 
 
-def rel_g(g, gref, floor=0.0):
-    """max over states of ||g - gref||_inf / max(||gref||_inf, floor)."""
-    return max(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), floor) for a, b in zip(g, gref))
+def rel_g(g, gref):
+    """max over states of ||g - gref||_inf / ||gref||_inf."""
+    return max(np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(g, gref))
 
 
 @pytest.fixture(scope="module")
@@ -103,9 +105,8 @@ def test_separable_n28_energy_and_gradient(sep_problem, c128):
     tol_e, tol_g = (1e-10, 1e-8) if c128 else (1e-5, 1e-5)
     sigma = pb.info.sigma_c
     assert rel_e(e[:ke], eref, sigma) <= tol_e
-    # FD of the closed form is accurate to ~1e-9; complex64 gradients carry an absolute error of about
-    # 1e-7 sigma_C, so states with a gradient below 1e-2 sigma_C are compared on that scale
-    assert rel_g(g[:ke], gref, 0.0 if c128 else 1e-2 * sigma) <= tol_g
+    # FD of the closed form is accurate to about 1e-9 relative
+    assert rel_g(g[:ke], gref) <= tol_g
 
 
 @pytest.fixture(scope="module")
@@ -135,7 +136,7 @@ def test_cluster_product_n28_energy_and_gradient(cluster_problem, c128):
             gref[b] += gb
     tol = 1e-10 if c128 else 1e-5
     assert rel_e(e[:ks], eref, pb.info.sigma_c) <= tol
-    assert rel_g(g[:ks], gref, 0.0 if c128 else 1e-2 * pb.info.sigma_c) <= tol
+    assert rel_g(g[:ks], gref) <= tol
 
 
 def test_workload_n28_complex64_vs_complex128_and_fd():
@@ -173,7 +174,59 @@ def test_benchmark_instance_vs_stored_oracle():
         b = s["start"]
         gr = np.array(s["gradient"])
         assert abs(e[b] - s["energy"]) / max(abs(s["energy"]), sigma) <= 1e-5, (b, e[b], s["energy"])
-        assert np.max(np.abs(g[b] - gr)) <= 1e-5 * max(np.max(np.abs(gr)), 1e-2 * sigma), (b, g[b], gr)
+        assert np.max(np.abs(g[b] - gr)) <= 1e-5 * np.max(np.abs(gr)), (b, g[b], gr)
+
+
+def test_benchmark_all_64_starts_vs_complex128():
+    """Every start of the timed wave: the complex64 energies and gradients (the timed launch
+    configuration) against the complex128 path in waves of 16, at 1e-5 relative with no floor; the
+    complex128 path itself against the stored oracle values of starts 0 and 1 at 1e-10."""
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "regular3_n28_p8_oracle.json")))
+    inst, x = W.workload3(batch=WAVE, p=8)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    pin_bench_schedule(pb, 8)
+    e64, g64 = pb.evaluate(x, grad=True)
+    e128, g128 = np.empty(WAVE), np.empty((WAVE, 16))
+    for w in range(0, WAVE, 16):
+        print(f"complex128 starts {w}..{w + 15}", flush=True)
+        e128[w:w + 16], g128[w:w + 16] = pb.evaluate(x[w:w + 16], grad=True, c128=True)
+    sigma = pb.info.sigma_c
+    for s in ref["starts"]:
+        b = s["start"]
+        assert abs(e128[b] - s["energy"]) / max(abs(s["energy"]), sigma) <= 1e-10
+        assert np.max(np.abs(g128[b] - np.array(s["gradient"]))) <= 1e-10 * np.max(np.abs(s["gradient"]))
+    de = np.abs(e64 - e128) / np.maximum(np.abs(e128), sigma)
+    dg = np.max(np.abs(g64 - g128), axis=1) / np.max(np.abs(g128), axis=1)
+    print(f"64 starts: energy rel max {de.max():.3e}, gradient rel max {dg.max():.3e}", flush=True)
+    assert de.max() <= 1e-5 and dg.max() <= 1e-5, (int(np.argmax(de)), int(np.argmax(dg)))
+
+
+def test_benchmark_topk_vs_stored_oracle():
+    """The 10 most probable basis indices of start 0 of the benchmark instance (complex64 and
+    complex128) against the oracle's, stored with their probabilities.  An index must match the
+    oracle's rank exactly where the oracle's gap to each neighbouring rank exceeds twice the
+    comparison bound (the rank is then decided); inside a closer group, the returned indices must be
+    the group's in some order.  Probabilities: within 1e-5 relative (complex64) or 1e-10 (complex128)."""
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "regular3_n28_p8_oracle.json")))
+    top = ref["top12_start0"]
+    ri, rp = np.array(top["index"]), np.array(top["probability"])
+    inst, x = W.workload3(batch=1, p=8)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    k = 10
+    for c128, tol in ((False, 1e-5), (True, 1e-10)):
+        idx, prob, cost = pb.topk(x[0], k=k, c128=c128)
+        idx = idx.astype(np.int64)
+        bound = 2 * tol * rp[0]
+        for r in range(k):
+            # the group of oracle ranks within `bound` of rank r (ranks 0..11 are stored)
+            grp = [j for j in range(len(ri)) if abs(rp[j] - rp[r]) <= bound]
+            if grp == [r]:
+                assert idx[r] == ri[r], (c128, r, idx[r], ri[r])
+            else:
+                assert idx[r] in set(ri[grp]), (c128, r, idx[r], ri[grp])
+            j = int(np.flatnonzero(ri == idx[r])[0])
+            assert abs(prob[r] - rp[j]) <= tol * rp[j], (c128, r, prob[r], rp[j])
+        print(f"top-10 c128={c128}: {[int(v) for v in idx]}", flush=True)
 
 
 def test_benchmark_cost_diagonal_bit_exact():
