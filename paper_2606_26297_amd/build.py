@@ -14,6 +14,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqaoa_qubo.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# host-only sources (no kernels): plain C++ against the HIP runtime headers, no device code objects
+CXX = os.environ.get("QQ_HOST_CXX", "/opt/rocm/llvm/bin/clang++")
+HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 ARCH = "gfx950"
 
 HIP_SOURCES = ["qq_kernels.hip", "qq_fast.hip", "qq_many.hip", "qq_optim.hip", "qq_plain.hip", "qq_sample.hip",
@@ -45,7 +48,7 @@ def build(verbose: bool = False, resource_usage: bool = False) -> str:
         jobs.append([HIPCC, *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     for src in CPP_SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
-        jobs.append([HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append([CXX, *COMMON, *HOST, "-c", os.path.join(CSRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=min(6, len(jobs))) as ex:
         outs = list(ex.map(lambda c: _run(c, verbose), jobs))
     if resource_usage:

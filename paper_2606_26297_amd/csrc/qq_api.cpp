@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -42,6 +43,41 @@ qq_status fail(qq_status st, const char *fmt, ...)
         hipError_t e_ = (expr);                                                                        \
         if (e_ != hipSuccess) return fail(QQ_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+// Opt-in debugging aids, read from the environment at each call:
+//   QQ_POISON  (non-empty, not "0"): fill every evaluation workspace with all-ones words (a NaN in
+//              float and double) before the evaluation's kernels run, so a read of a byte that the
+//              call has not written first turns its results into NaN;
+//   QQ_LOG     (non-empty, not "0"): one line per evaluation call on stderr (entry point, sizes,
+//              flags, status, host wall time).
+bool env_flag(const char *name)
+{
+    const char *v = std::getenv(name);
+    return v && *v && std::strcmp(v, "0") != 0;
+}
+
+hipError_t poison(void *ws, size_t bytes, hipStream_t stream)
+{
+    if (!env_flag("QQ_POISON") || bytes < 4) return hipSuccess;
+    return launch_fill_u32(static_cast<uint32_t *>(ws), 0xffffffffu, bytes / 4, stream);
+}
+
+struct CallLog {
+    const char *name;
+    int n, p, batch, flags;
+    std::chrono::steady_clock::time_point t0;
+    qq_status st = QQ_OK;
+    CallLog(const char *nm, int n_, int p_, int b_, int f_)
+        : name(nm), n(n_), p(p_), batch(b_), flags(f_), t0(std::chrono::steady_clock::now()) {}
+    qq_status operator()(qq_status s) { st = s; return s; }
+    ~CallLog()
+    {
+        if (!env_flag("QQ_LOG")) return;
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "[qq] %s n=%d p=%d batch=%d flags=0x%x status=%d %.3f ms%s%s\n", name, n, p, batch, flags,
+                     (int)st, ms, st == QQ_OK ? "" : ": ", st == QQ_OK ? "" : g_err.c_str());
+    }
+};
 
 constexpr int kTelegateMaxN = 26;  // n + 2 qubits of complex128: 4 GiB
 constexpr double kTwo31 = 2147483648.0;
@@ -1106,6 +1142,65 @@ qq_status set_error(qq_status st, const char *msg)
 int problem_device(const qq_problem *pb) { return pb->device; }
 }  // namespace qq
 
+namespace {
+
+// Bound on ||dg||_inf of a complex64 gradient (see qq_evaluate_guarded in the header): a part relative
+// to the gradient, and the random part of the rounding of 2^n stored amplitudes in sums whose terms
+// carry (C - alpha)^2, which grows as 2^(-n/2) of sigma_C^2 per unit rounding.
+double c64_grad_bound(int n, double sigma_c, double gmax)
+{
+    return QQ_GUARD_REL * gmax + QQ_GUARD_K * std::ldexp(sigma_c * sigma_c, -24) * std::pow(2.0, -0.5 * n);
+}
+
+constexpr double kC128GradRel = 1e-10;
+
+double max_abs(const double *g, int m)
+{
+    double r = 0.0;
+    for (int j = 0; j < m; ++j) r = std::max(r, std::fabs(g[j]));
+    return r;
+}
+
+// Recompute the flagged parameter sets of one problem with complex128 states (host in, host out).
+qq_status recompute_c128(qq_problem *pb, int p, const double *params, const std::vector<int> &sets, int flags,
+                         void *stream, double *energy, double *grad)
+{
+    if (sets.empty()) return QQ_OK;
+    const int m = (int)sets.size(), w = 2 * p;
+    std::vector<double> x((size_t)m * w), e(m), g((size_t)m * w);
+    for (int i = 0; i < m; ++i) std::memcpy(&x[(size_t)i * w], params + (size_t)sets[i] * w, w * sizeof(double));
+    const int f = (flags & (QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED)) | QQ_C128;
+    if (qq_status st = qq_evaluate(pb, p, m, x.data(), f, nullptr, 0, stream, e.data(), g.data()); st != QQ_OK)
+        return st;
+    for (int i = 0; i < m; ++i) {
+        energy[sets[i]] = e[i];
+        std::memcpy(grad + (size_t)sets[i] * w, &g[(size_t)i * w], w * sizeof(double));
+    }
+    return QQ_OK;
+}
+
+// Decide, for the complex64 results of one problem, which sets to recompute; fill the outputs.
+std::vector<int> guard_sets(const qq_problem *pb, int p, int batch, const double *grad, double tol, bool c128_all,
+                            int32_t *c128_out, double *err_out)
+{
+    std::vector<int> sets;
+    for (int b = 0; b < batch; ++b) {
+        const double gmax = grad ? max_abs(grad + (size_t)b * 2 * p, 2 * p) : 0.0;
+        bool up = c128_all;
+        double err = 0.0;
+        if (grad && !c128_all) {
+            err = c64_grad_bound(pb->n, pb->sigma_c, gmax);
+            up = err > tol * gmax;
+        }
+        if (up && grad && !c128_all) sets.push_back(b);
+        if (c128_out) c128_out[b] = up ? 1 : 0;
+        if (err_out) err_out[b] = grad ? (up ? kC128GradRel * gmax : err) : 0.0;
+    }
+    return sets;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *qq_last_error(void) { return g_err.c_str(); }
@@ -1467,7 +1562,7 @@ qq_status qq_workspace_size(const qq_problem *pb, int p, int batch, int flags, s
     return QQ_OK;
 }
 
-qq_status qq_evaluate(qq_problem *pb, int p, int batch, const double *params, int flags, void *workspace,
+static qq_status evaluate_impl(qq_problem *pb, int p, int batch, const double *params, int flags, void *workspace,
                       size_t ws_bytes, void *stream_, double *energy_out, double *grad_out)
 {
     g_err.clear();
@@ -1490,6 +1585,7 @@ qq_status qq_evaluate(qq_problem *pb, int p, int batch, const double *params, in
     } else if (ws_bytes < L.total) {
         return fail(QQ_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
     }
+    QQ_HIP(poison(ws, L.total, stream));
     if (qq_status st = eval_core(pb, p, batch, params, flags, plan, L, ws, stream); st != QQ_OK) return st;
     const double *d_out = reinterpret_cast<const double *>(ws + L.out);
     const size_t nout = 1 + 2 * (size_t)p;
@@ -1528,6 +1624,7 @@ static qq_status state_into(qq_problem *pb, int p, const double *params, int fla
     QQ_HIP(hipSetDevice(pb->device));
     if (qq_status st = check_device_fits(pb->device, L.total, "the state"); st != QQ_OK) return st;
     if (hipMalloc(&own.p, L.total) != hipSuccess) return fail(QQ_E_NOMEM, "hipMalloc(%zu) failed", L.total);
+    QQ_HIP(poison(own.p, L.total, stream));
     return eval_core(pb, p, 1, params, f, plan, L, static_cast<char *>(own.p), stream);
 }
 
@@ -1839,7 +1936,7 @@ qq_status qq_workspace_size_many(int count, qq_problem *const *problems, const i
     return QQ_OK;
 }
 
-qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p, const int *batch,
+static qq_status evaluate_many_impl(int count, qq_problem *const *problems, const int *p, const int *batch,
                            const double *const *params, int flags, const qq_many_options *opt, void *workspace,
                            size_t ws_bytes, void *stream_, double *const *energy_out, double *const *grad_out)
 {
@@ -1870,6 +1967,7 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
     } else if (ws_bytes < M.total) {
         return fail(QQ_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, M.total);
     }
+    QQ_HIP(poison(ws, M.total, stream));
     int rate_khz = 0;
     QQ_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device));
     const double wait_ms = (opt && opt->wait_limit_ms > 0.0) ? opt->wait_limit_ms : kDefaultWaitMs;
@@ -1978,66 +2076,7 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
     return QQ_OK;
 }
 
-namespace {
-
-// Bound on ||dg||_inf of a complex64 gradient (see qq_evaluate_guarded in the header): a part relative
-// to the gradient, and the random part of the rounding of 2^n stored amplitudes in sums whose terms
-// carry (C - alpha)^2, which grows as 2^(-n/2) of sigma_C^2 per unit rounding.
-double c64_grad_bound(int n, double sigma_c, double gmax)
-{
-    return QQ_GUARD_REL * gmax + QQ_GUARD_K * std::ldexp(sigma_c * sigma_c, -24) * std::pow(2.0, -0.5 * n);
-}
-
-constexpr double kC128GradRel = 1e-10;
-
-double max_abs(const double *g, int m)
-{
-    double r = 0.0;
-    for (int j = 0; j < m; ++j) r = std::max(r, std::fabs(g[j]));
-    return r;
-}
-
-// Recompute the flagged parameter sets of one problem with complex128 states (host in, host out).
-qq_status recompute_c128(qq_problem *pb, int p, const double *params, const std::vector<int> &sets, int flags,
-                         void *stream, double *energy, double *grad)
-{
-    if (sets.empty()) return QQ_OK;
-    const int m = (int)sets.size(), w = 2 * p;
-    std::vector<double> x((size_t)m * w), e(m), g((size_t)m * w);
-    for (int i = 0; i < m; ++i) std::memcpy(&x[(size_t)i * w], params + (size_t)sets[i] * w, w * sizeof(double));
-    const int f = (flags & (QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED)) | QQ_C128;
-    if (qq_status st = qq_evaluate(pb, p, m, x.data(), f, nullptr, 0, stream, e.data(), g.data()); st != QQ_OK)
-        return st;
-    for (int i = 0; i < m; ++i) {
-        energy[sets[i]] = e[i];
-        std::memcpy(grad + (size_t)sets[i] * w, &g[(size_t)i * w], w * sizeof(double));
-    }
-    return QQ_OK;
-}
-
-// Decide, for the complex64 results of one problem, which sets to recompute; fill the outputs.
-std::vector<int> guard_sets(const qq_problem *pb, int p, int batch, const double *grad, double tol, bool c128_all,
-                            int32_t *c128_out, double *err_out)
-{
-    std::vector<int> sets;
-    for (int b = 0; b < batch; ++b) {
-        const double gmax = grad ? max_abs(grad + (size_t)b * 2 * p, 2 * p) : 0.0;
-        bool up = c128_all;
-        double err = 0.0;
-        if (grad && !c128_all) {
-            err = c64_grad_bound(pb->n, pb->sigma_c, gmax);
-            up = err > tol * gmax;
-        }
-        if (up && grad && !c128_all) sets.push_back(b);
-        if (c128_out) c128_out[b] = up ? 1 : 0;
-        if (err_out) err_out[b] = grad ? (up ? kC128GradRel * gmax : err) : 0.0;
-    }
-    return sets;
-}
-
-}  // namespace
-
-qq_status qq_evaluate_guarded(qq_problem *pb, int p, int batch, const double *params, int flags, double tol,
+static qq_status evaluate_guarded_impl(qq_problem *pb, int p, int batch, const double *params, int flags, double tol,
                               void *stream, double *energy_out, double *grad_out, int32_t *c128_out,
                               double *grad_err_out)
 {
@@ -2070,7 +2109,7 @@ qq_status qq_evaluate_guarded(qq_problem *pb, int p, int batch, const double *pa
     return QQ_OK;
 }
 
-qq_status qq_evaluate_many_guarded(int count, qq_problem *const *problems, const int *p, const int *batch,
+static qq_status evaluate_many_guarded_impl(int count, qq_problem *const *problems, const int *p, const int *batch,
                                    const double *const *params, int flags, const qq_many_options *opt, double tol,
                                    void *stream, double *const *energy_out, double *const *grad_out,
                                    int32_t *const *c128_out, double *const *grad_err_out)
@@ -2553,6 +2592,43 @@ qq_status qq_evaluate_plain(qq_problem *pb, int p, const double *params, int fla
     if (grad)
         for (int j = 0; j < 2 * p; ++j) grad_out[j] = h[1 + j];
     return QQ_OK;
+}
+
+// ---- public evaluation entry points (QQ_LOG: one line per call) ------------------------------
+
+qq_status qq_evaluate(qq_problem *pb, int p, int batch, const double *params, int flags, void *workspace,
+                      size_t ws_bytes, void *stream, double *energy_out, double *grad_out)
+{
+    CallLog log("qq_evaluate", pb ? pb->n : -1, p, batch, flags);
+    return log(evaluate_impl(pb, p, batch, params, flags, workspace, ws_bytes, stream, energy_out, grad_out));
+}
+
+qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p, const int *batch,
+                           const double *const *params, int flags, const qq_many_options *opt, void *workspace,
+                           size_t ws_bytes, void *stream, double *const *energy_out, double *const *grad_out)
+{
+    CallLog log("qq_evaluate_many", count, -1, -1, flags);
+    return log(evaluate_many_impl(count, problems, p, batch, params, flags, opt, workspace, ws_bytes, stream,
+                                  energy_out, grad_out));
+}
+
+qq_status qq_evaluate_guarded(qq_problem *pb, int p, int batch, const double *params, int flags, double tol,
+                              void *stream, double *energy_out, double *grad_out, int32_t *c128_out,
+                              double *grad_err_out)
+{
+    CallLog log("qq_evaluate_guarded", pb ? pb->n : -1, p, batch, flags);
+    return log(evaluate_guarded_impl(pb, p, batch, params, flags, tol, stream, energy_out, grad_out, c128_out,
+                                     grad_err_out));
+}
+
+qq_status qq_evaluate_many_guarded(int count, qq_problem *const *problems, const int *p, const int *batch,
+                                   const double *const *params, int flags, const qq_many_options *opt, double tol,
+                                   void *stream, double *const *energy_out, double *const *grad_out,
+                                   int32_t *const *c128_out, double *const *grad_err_out)
+{
+    CallLog log("qq_evaluate_many_guarded", count, -1, -1, flags);
+    return log(evaluate_many_guarded_impl(count, problems, p, batch, params, flags, opt, tol, stream, energy_out,
+                                          grad_out, c128_out, grad_err_out));
 }
 
 }  // extern "C"
