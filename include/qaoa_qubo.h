@@ -229,6 +229,29 @@ qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p,
                            size_t ws_bytes, void *stream, double *const *energy_out, double *const *grad_out);
 
 /*
+ * qq_evaluate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, arguments, flags, outputs and errors as qq_evaluate, with
+ * the workspace taken from a fixed device array of QQ_STATIC_SCRATCH_BYTES
+ * owned by the library instead of a caller buffer.  The call performs no
+ * device allocation or free.  Each GPU the library runs on holds its own copy
+ * of the array from the first such call on it until the process ends.
+ *   Limit: requests whose workspace (qq_workspace_size) exceeds
+ *   QQ_STATIC_SCRATCH_BYTES are rejected with QQ_E_WORKSPACE before any device
+ *   work (complex64: n = 20 holds up to 7 parameter sets with gradients,
+ *   n = 21 three, n = 22 one).
+ *   Every call on a GPU shares that GPU's array, which keeps the last call's
+ *   contents: calls that overlap on one GPU (other streams or threads) race
+ *   and must be serialised by the caller.  Nothing in the array needs to start
+ *   at zero: every byte a call reads there was written earlier in that call.
+ *   Per-launch profiling (qq_profile_enable) records nothing for these calls.
+ */
+#define QQ_STATIC_SCRATCH_BYTES (128u << 20)
+
+qq_status qq_evaluate_static(qq_problem *prob, int p, int batch, const double *params, int flags, void *stream,
+                             double *energy_out, double *grad_out);
+
+/*
  * Evaluation with every gradient held to a relative tolerance (the error
  * against exact arithmetic stated per result).  Same objective and gradient
  * as qq_evaluate / qq_evaluate_many (eq. (17), adjoint derivatives in the

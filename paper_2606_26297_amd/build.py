@@ -20,7 +20,7 @@ HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 ARCH = "gfx950"
 
 HIP_SOURCES = ["qq_kernels.hip", "qq_fast.hip", "qq_many.hip", "qq_optim.hip", "qq_plain.hip", "qq_sample.hip",
-               "qq_telegate.hip"]
+               "qq_telegate.hip", "qq_static.hip"]
 CPP_SOURCES = ["qq_api.cpp", "qq_driver.cpp", "qq_alloc.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

@@ -1610,6 +1610,48 @@ static qq_status evaluate_impl(qq_problem *pb, int p, int batch, const double *p
     return QQ_OK;
 }
 
+static qq_status evaluate_static_impl(qq_problem *pb, int p, int batch, const double *params, int flags, void *stream_,
+                             double *energy_out, double *grad_out)
+{
+    g_err.clear();
+    if (qq_status st = validate_eval(pb, p, batch, flags); st != QQ_OK) return st;
+    if (!params) return fail(QQ_E_INVALID, "params is NULL");
+    if (!energy_out) return fail(QQ_E_INVALID, "energy_out is NULL");
+    if ((flags & QQ_GRAD) && !grad_out) return fail(QQ_E_INVALID, "QQ_GRAD requires grad_out");
+    if (!(flags & QQ_PARAMS_ON_DEVICE))
+        if (qq_status st = check_params_host(params, (size_t)batch * 2 * p); st != QQ_OK) return st;
+    const Plan plan = plan_for(pb, p, batch, flags, false);
+    const Layout L = layout_for(pb, p, batch, flags, plan);
+    if (L.total > (size_t)QQ_STATIC_SCRATCH_BYTES)
+        return fail(QQ_E_WORKSPACE, "this evaluation needs %zu bytes of workspace; the fixed scratch array holds %zu",
+                    L.total, (size_t)QQ_STATIC_SCRATCH_BYTES);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    QQ_HIP(hipSetDevice(pb->device));
+    void *sp = nullptr;
+    QQ_HIP(static_scratch(pb->device, &sp));
+    char *ws = static_cast<char *>(sp);
+    QQ_HIP(poison(ws, L.total, stream));
+    const double *d_params = params;
+    if (!(flags & QQ_PARAMS_ON_DEVICE)) {
+        d_params = reinterpret_cast<const double *>(ws + L.params);
+        QQ_HIP(hipMemcpyAsync(ws + L.params, params, (size_t)batch * 2 * p * sizeof(double), hipMemcpyHostToDevice,
+                              stream));
+    }
+    // no profiling events here (capturing = true): they are not part of the computation
+    if (qq_status st = run_plan(pb, plan, L, p, batch, flags, ws, d_params, stream, true); st != QQ_OK) return st;
+    const double *d_out = reinterpret_cast<const double *>(ws + L.out);
+    const size_t nout = 1 + 2 * (size_t)p;
+    const bool grad = flags & QQ_GRAD;
+    const hipMemcpyKind kind = (flags & QQ_OUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    QQ_HIP(hipMemcpy2DAsync(energy_out, sizeof(double), d_out, nout * sizeof(double), sizeof(double), batch, kind,
+                            stream));
+    if (grad)
+        QQ_HIP(hipMemcpy2DAsync(grad_out, 2 * p * sizeof(double), d_out + 1, nout * sizeof(double),
+                                2 * p * sizeof(double), batch, kind, stream));
+    if (!(flags & QQ_OUT_ON_DEVICE)) QQ_HIP(hipStreamSynchronize(stream));
+    return QQ_OK;
+}
+
 // Forward evaluation of one parameter set with the final state kept in `own`.
 static qq_status state_into(qq_problem *pb, int p, const double *params, int flags, hipStream_t stream, DevBuf &own,
                             Layout &L)
@@ -2601,6 +2643,13 @@ qq_status qq_evaluate(qq_problem *pb, int p, int batch, const double *params, in
 {
     CallLog log("qq_evaluate", pb ? pb->n : -1, p, batch, flags);
     return log(evaluate_impl(pb, p, batch, params, flags, workspace, ws_bytes, stream, energy_out, grad_out));
+}
+
+qq_status qq_evaluate_static(qq_problem *pb, int p, int batch, const double *params, int flags, void *stream,
+                             double *energy_out, double *grad_out)
+{
+    CallLog log("qq_evaluate_static", pb ? pb->n : -1, p, batch, flags);
+    return log(evaluate_static_impl(pb, p, batch, params, flags, stream, energy_out, grad_out));
 }
 
 qq_status qq_evaluate_many(int count, qq_problem *const *problems, const int *p, const int *batch,

@@ -160,6 +160,10 @@ struct FastPassParams {
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
 
+// Device address of the fixed scratch array (QQ_STATIC_SCRATCH_BYTES) on `device`, taken once per
+// device with hipGetSymbolAddress (qq_static.hip).
+hipError_t static_scratch(int device, void **ptr);
+
 // Persistent launch over many problems (qq_many.hip).
 // Work item = (problem, state b, pass j, chunk c): tiles [c * tpc, min((c + 1) * tpc, tiles))
 // of pass j.  Items are numbered level-major (every problem's pass 0, then every

@@ -35,6 +35,7 @@ QQ_C128 = 8
 QQ_PARAMS_ON_DEVICE = 16
 QQ_OUT_ON_DEVICE = 32
 
+QQ_STATIC_SCRATCH_BYTES = 128 << 20
 QQ_GUARD_REL = 4e-6
 QQ_GUARD_K = 40.0
 
@@ -120,6 +121,7 @@ SIGNATURES = {
     "qq_probabilities": ([_vp, _int, _vp, _int, _vp, _vp], _int),
     "qq_topk": ([_vp, _int, _vp, _int, _int, _u64p, _dp, _dp, _vp], _int),
     "qq_evaluate_plain": ([_vp, _int, _dp, _int, _vp, _dp, _dp], _int),
+    "qq_evaluate_static": ([_vp, _int, _int, _vp, _int, _vp, _vp, _vp], _int),
     "qq_evaluate_guarded": ([_vp, _int, _int, _vp, _int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp], _int),
     "qq_evaluate_many_guarded": ([_int, _vp, _vp, _vp, _vp, _int, ctypes.POINTER(QQManyOptions), ctypes.c_double,
                                   _vp, _vp, _vp, _vp, _vp], _int),
@@ -351,6 +353,15 @@ def qq_evaluate_plain(handle, p, params, flags, stream=None):
     g = np.zeros(2 * p)
     _check(lib().qq_evaluate_plain(handle, int(p), _ptr(x), int(flags), _stream_ptr(stream), _ptr(e), _ptr(g)))
     return float(e[0]), g
+
+
+def qq_evaluate_static(handle, p, batch, params, flags, stream, energy_out, grad_out):
+    """qq_evaluate with the library's fixed scratch array as workspace (no device allocation)."""
+    pp = _buf(params, _need(p, batch, lambda q: 2 * q), "params", flags & QQ_PARAMS_ON_DEVICE, _F64)
+    ep = _buf(energy_out, _need(p, batch, lambda q: 1), "energy_out", flags & QQ_OUT_ON_DEVICE, _F64)
+    gp = None if grad_out is None else _buf(grad_out, _need(p, batch, lambda q: 2 * q), "grad_out",
+                                            flags & QQ_OUT_ON_DEVICE, _F64)
+    _check(lib().qq_evaluate_static(handle, int(p), int(batch), pp, int(flags), _stream_ptr(stream), ep, gp))
 
 
 def qq_evaluate_guarded(handle, p, batch, params, flags, tol, energy_out, grad_out, c128_out=None,
