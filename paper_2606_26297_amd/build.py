@@ -61,5 +61,34 @@ def build(verbose: bool = False, resource_usage: bool = False) -> str:
     return LIB
 
 
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the host-side sources (validation, planning,
+# allocation strategies, search driver) for CPU tests: they are compiled again with the sanitizers
+# and linked with the device objects of the regular build into a separate library.  The sanitizer
+# runtime is not linked in; the test that loads this library preloads it.
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+SAN_DIR = os.path.join(BUILD_DIR, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libqaoa_qubo_san.so")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    dev_objs = [os.path.join(BUILD_DIR, s + ".o") for s in HIP_SOURCES]
+    if not all(os.path.exists(o) for o in dev_objs):
+        build(verbose)
+    os.makedirs(SAN_DIR, exist_ok=True)
+    objs = []
+    for src in CPP_SOURCES:
+        obj = os.path.join(SAN_DIR, src + ".o")
+        _run([CXX, "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", *SAN_FLAGS, *HOST, "-c",
+              os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    tmp = SAN_LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *dev_objs], verbose)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="--verbose" in sys.argv, resource_usage="--resource-usage" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="--verbose" in sys.argv))
+    else:
+        print(build(verbose="--verbose" in sys.argv, resource_usage="--resource-usage" in sys.argv))
