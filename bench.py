@@ -195,8 +195,10 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def uneven_batch(dev, reps=5):
-    """The 512-problem uneven batch: persistent launch vs per-problem launches (device-resident)."""
+def uneven_batch(dev, reps=5, pinned=None, persistent_only=False):
+    """The 512-problem uneven batch: persistent launch vs per-problem launches (device-resident).
+    pinned: persistent-launch options to use instead of autotuning them; persistent_only: skip the
+    per-problem launches (about 26 000 dispatches)."""
     import numpy as np
     import torch
 
@@ -214,7 +216,10 @@ def uneven_batch(dev, reps=5):
     es = [torch.empty(b, dtype=torch.float64, device=dev) for b in bs]
     gs = [torch.empty(x.shape, dtype=torch.float64, device=dev) for x in xs]
     stream = torch.cuda.current_stream(dev)
-    opt, tune_ms = N.qq_autotune_many(handles, ps, bs, flags, None, stream)
+    if pinned is None:
+        opt, tune_ms = N.qq_autotune_many(handles, ps, bs, flags, None, stream)
+    else:
+        opt, tune_ms = dict(pinned), None
     ws_bytes = N.qq_workspace_size_many(handles, ps, bs, flags, opt)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
@@ -237,6 +242,10 @@ def uneven_batch(dev, reps=5):
     e_many = [e.clone() for e in es]
     g_many = [g.clone() for g in gs]
     del ws
+    if persistent_only:
+        return {"workload": "512 dense integer QUBOs, n ~ U{10..22}, p ~ U{1..6}, 1 parameter set each, energy+grad",
+                "persistent_ms": round(1000 * t_many, 3), "persistent_kernel_ms": round(k_ms, 3),
+                "persistent_algorithmic_GBps": round(k_bytes / (k_ms / 1000.0) / 1e9, 1), "options": opt}
     wsz = max(N.qq_workspace_size(h, p, b, flags) for h, p, b in zip(handles, ps, bs))
     ws1 = torch.empty(wsz, dtype=torch.uint8, device=dev)
 
@@ -278,8 +287,32 @@ def uneven_batch(dev, reps=5):
             "per_problem_ms": round(1000 * t_per, 3), "per_problem_launches": launches,
             "speedup": round(t_per / t_many, 2), "problems_per_s": round(len(items) / t_many, 1),
             "traffic_bytes_per_launch": load_traffic("many_kernel<%s>" % N.DIAG_TYPE_NAMES[pbs[0].info.diag_bytes]),
-            "options": opt, "autotune_best_ms": round(tune_ms, 3),
+            "options": opt, "autotune_best_ms": None if tune_ms is None else round(tune_ms, 3),
             "energy_rel_vs_per_problem": de, "vs_oracle": vs_oracle}
+
+
+def copy_calibration(dev):
+    """A plain copy kernel of known size (4 GiB read, 4 GiB written): its FETCH_SIZE / WRITE_SIZE counters
+    calibrate the counter-derived HBM traffic of the other kernels, and its rate is a bandwidth reference."""
+    import torch
+
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    c0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    cms = c0.elapsed_time(c1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "ms_per_copy": round(cms, 4), "read_plus_write_GBps": round(2 * nbytes / (cms / 1e3) / 1e9, 1),
+            "kernel": "torch copy_ of a 4 GiB float32 tensor (device to device)"}
 
 
 def small_workloads(dev, reps=200):
@@ -499,13 +532,23 @@ def multi_qpu(dev):
 
     inst, x, alloc = W.workload5()
     n, p, B = inst.H.shape[0], x.shape[1] // 2, x.shape[0]
+    N.qq_profile_enable(True)
+    N.qq_profile_read()
     pb = Problem(inst.H, inst.f, inst.c0, device=0)
+    torch.cuda.synchronize()
+    diag_recs = [r for r in N.qq_profile_read() if r["kind"] == 5]
+    N.qq_profile_enable(False)
     caps = [int(c) for c in np.bincount(alloc)]
     cross, remote = pb.set_allocation(alloc, len(caps), caps)
     xt = torch.tensor(x, device=dev)
     out = {"workload": f"dense N(0,1) upper-triangular QUBO, n = {n}, p = {p}, {B} parameter sets, "
                        f"{len(caps)} QPUs x {caps[0]} (contiguous), complex64 energy+grad",
            "cross_terms": cross, "remote_cx_per_layer": remote, "remote_cx_circuit": remote * p}
+    if diag_recs:
+        r = diag_recs[0]
+        out["cost_diag_kernel"] = {"ms": round(r["ms"], 3), "written_GBps": round(r["bytes"] / (r["ms"] / 1e3) / 1e9, 1),
+                                   "entries": 1 << n, "terms_per_entry": n + int(np.count_nonzero(np.triu(inst.H, 1))),
+                                   "note": "FP64 entries in the canonical summation order, once per problem"}
     res = {}
     for name, part in (("monolithic", False), ("partitioned", True)):
         pb.evaluate(xt, grad=True, partitioned=part)
@@ -538,6 +581,118 @@ def multi_qpu(dev):
     return out
 
 
+def _short_kernel_name(name: str) -> str:
+    """rocprofv3's demangled kernel name without the return type, namespaces and parameter list."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    name = name.replace("qq::(anonymous namespace)::", "").replace("qq::", "")
+    depth = 0
+    for i, ch in enumerate(name):  # cut at the parameter list: the first '(' outside template brackets
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and i > 0:
+            return name[:i]
+    return name
+
+
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    import glob
+
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    return rows
+
+
+def summarize_counters(workload, stats_dir, fetch_dir, write_dir, command, only=None):
+    """Summaries of three rocprofv3 runs of one command: kernel statistics (--kernel-trace --stats) and the
+    FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch), each calibrated by a 4 GiB reference copy
+    (its counter reading against the 4 GiB it moves).  Per-launch figures use only the dispatches of each
+    kernel with its most frequent grid size (the timed configuration); the others are listed apart."""
+    from collections import Counter, defaultdict
+
+    stats = _csv_rows(stats_dir, "kernel_stats.csv")
+    lines = [f"# rocprofv3 kernel statistics: {workload}", "",
+             "Command (on the MI355X box, repository at /root/repo):", "",
+             "    cd /tmp && export TMPDIR=/tmp",
+             f"    rocprofv3 --kernel-trace --stats -f csv -d <out>/stats -o run -- {command}", "",
+             "| kernel | calls | avg ms | min ms | max ms | share % |", "|---|---:|---:|---:|---:|---:|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| `{_short_kernel_name(r['Name'])[:70]}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                     f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    with open(os.path.join(ROOT, "profiles", f"{workload}_stats.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    def per_kernel(directory, counter):
+        rows = [r for r in _csv_rows(directory, "counter_collection.csv") if r["Counter_Name"].startswith(counter)]
+        by = defaultdict(list)
+        for r in rows:
+            by[(_short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size"]))].append(float(r["Counter_Value"]) * 1024.0)
+        copies = [v for (k, g), vs in by.items() if "copyBuffer" in k for v in vs]
+        return by, max(copies) if copies else None
+
+    fetch, f_copy = per_kernel(fetch_dir, "FETCH_SIZE")
+    write, w_copy = per_kernel(write_dir, "WRITE_SIZE")
+    ref = 4.0 * 2 ** 30
+    f_scale = ref / f_copy if f_copy else 1.0
+    w_scale = ref / w_copy if w_copy else 1.0
+    names = sorted({k for k, _ in fetch} | {k for k, _ in write})
+    grid_count = Counter()
+    for (k, g), vs in list(fetch.items()) + list(write.items()):
+        grid_count[(k, g)] += len(vs)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    traffic = {"kernel_src_sha256_16": kernel_hash(), "workloads": {}, "kernels": {}}
+    if os.path.exists(path):
+        with open(path) as fh:
+            old = json.load(fh)
+        if old.get("kernel_src_sha256_16") == traffic["kernel_src_sha256_16"]:
+            traffic = old
+            traffic.setdefault("workloads", {})
+    traffic["workloads"][workload] = command
+    tl = [f"# rocprofv3 HBM traffic counters: {workload}", "",
+          "Two counter runs (one counter per run) of the same command:", "",
+          "    cd /tmp && export TMPDIR=/tmp",
+          f"    timeout -s KILL 600 rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/fetch -o run -- {command}",
+          f"    timeout -s KILL 600 rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/write -o run -- {command}", "",
+          f"Calibration: the 4 GiB reference copy reads FETCH_SIZE = {f_copy / 2 ** 30 if f_copy else float('nan'):.3f} GiB "
+          f"and WRITE_SIZE = {w_copy / 2 ** 30 if w_copy else float('nan'):.3f} GiB, so fetch counters are scaled by "
+          f"{f_scale:.3f} and write counters by {w_scale:.3f}.  Per-launch rows use each kernel's dispatches of its "
+          "most frequent grid size (the timed configuration).", "",
+          "| kernel | grid (work-items) | launches | fetch GiB/launch | write GiB/launch | HBM GiB/launch |",
+          "|---|---:|---:|---:|---:|---:|"]
+    import re
+
+    for k in names:
+        if "copyBuffer" in k or "fillBuffer" in k or (only and not re.search(only, k)):
+            continue
+        grids = [g for (kk, g) in grid_count if kk == k]
+        g = max(grids, key=lambda gg: (grid_count[(k, gg)], gg))
+        fv, wv = fetch.get((k, g), []), write.get((k, g), [])
+        if not fv or not wv:
+            continue
+        fb = sum(fv) / len(fv) * f_scale
+        wb = sum(wv) / len(wv) * w_scale
+        traffic["kernels"][k] = {"hbm_bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                                 "grid_size": g, "launches": len(fv), "workload": workload}
+        others = sum(len(vs) for (kk, gg), vs in fetch.items() if kk == k and gg != g)
+        note = f" (+{others} launches of other sizes)" if others else ""
+        tl.append(f"| `{k}`{note} | {g} | {len(fv)} | {fb / 2 ** 30:.2f} | {wb / 2 ** 30:.2f} | {(fb + wb) / 2 ** 30:.2f} |")
+    with open(os.path.join(ROOT, "profiles", f"{workload}_traffic.md"), "w") as fh:
+        fh.write("\n".join(tl) + "\n")
+    with open(path, "w") as fh:
+        json.dump(traffic, fh, indent=1)
+        fh.write("\n")
+    print(f"wrote profiles/{workload}_stats.md, profiles/{workload}_traffic.md, profiles/traffic.json")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -560,6 +715,19 @@ def main():
     ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER[:SETORDER]]",
                     help="pin this schedule (workgroups per state, set pairing, tile order, set order) "
                          "instead of autotuning")
+    ap.add_argument("--persistent-only", action="store_true",
+                    help="with --uneven-only: time only the persistent launch (no per-problem launches)")
+    ap.add_argument("--aux-only", action="store_true",
+                    help="run only the cost-diagonal / probabilities / top-k leg on the timed instance")
+    ap.add_argument("--many-options", default=None, metavar="TILES_PER_CHUNK:MAX_WORKGROUPS",
+                    help="pin the persistent-launch options of the uneven batch instead of autotuning them")
+    ap.add_argument("--summarize-counters", nargs=5, default=None,
+                    metavar=("WORKLOAD", "STATS_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
+                    help="write the profiles/ summaries of three rocprofv3 runs of COMMAND (kernel statistics, "
+                         "FETCH_SIZE, WRITE_SIZE) and merge their per-launch HBM bytes into profiles/traffic.json; "
+                         "CPU only")
+    ap.add_argument("--counter-kernels", default=None, metavar="REGEX",
+                    help="with --summarize-counters: record per-launch traffic only for kernels matching REGEX")
     ap.add_argument("--no-aux", action="store_true",
                     help="skip the cost-diagonal / probabilities / top-k leg (one-state launches)")
     ap.add_argument("--no-small", action="store_true",
@@ -569,6 +737,9 @@ def main():
                          "report its rate")
     args = ap.parse_args()
 
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, only=args.counter_kernels)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library runs its hot path on a single MI355X "
               "(sharding over several GPUs is not built). Run with --gpus 1.", file=sys.stderr)
@@ -583,9 +754,24 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    pinned_many = None
+    if args.many_options:
+        tpc, cap = (int(v) for v in args.many_options.split(":"))
+        pinned_many = {"tiles_per_chunk": tpc, "max_workgroups": cap, "wait_limit_ms": 0.0}
     if args.uneven_only:
         progress("uneven batch")
-        print(json.dumps({"uneven_batch": uneven_batch(dev)}), flush=True)
+        res = {"uneven_batch": uneven_batch(dev, pinned=pinned_many, persistent_only=args.persistent_only)}
+        if args.copy_calibration:
+            res["copy_calibration"] = copy_calibration(dev)
+        print(json.dumps(res), flush=True)
+        return
+    if args.aux_only:
+        progress("cost diagonal, probabilities, top-k")
+        inst, x = W.workload3(batch=1, p=args.p, n=args.n)
+        res = {"aux": aux_kernels(dev, inst, x)}
+        if args.copy_calibration:
+            res["copy_calibration"] = copy_calibration(dev)
+        print(json.dumps(res), flush=True)
         return
     inst, x = W.workload3(batch=args.starts, p=args.p, n=args.n)
     pb = Problem(inst.H, inst.f, inst.c0, device=0)
@@ -679,25 +865,7 @@ def main():
     torch.cuda.empty_cache()
 
     if args.copy_calibration:
-        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
-        # counter-derived HBM traffic of the pass kernels
-        nbytes = 4 << 30
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 3
-        c0.record()
-        for _ in range(reps):
-            dst.copy_(src)
-        c1.record()
-        torch.cuda.synchronize()
-        cms = c0.elapsed_time(c1) / reps
-        out["copy_calibration"] = {"bytes": nbytes, "ms_per_copy": round(cms, 4),
-                                   "read_plus_write_GBps": round(2 * nbytes / (cms / 1000.0) / 1e9, 1),
-                                   "kernel": "torch copy_ of a 4 GiB float32 tensor (device to device)"}
-        del src, dst
+        out["copy_calibration"] = copy_calibration(dev)
     if not args.no_check:
         # sampled parity at full size: complex64 timed path vs the complex128 fused path (both GPU)
         e64 = e_out[:2].cpu().numpy()
@@ -748,7 +916,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_uneven:
         progress("uneven batch")
-        out["uneven_batch"] = uneven_batch(dev)
+        out["uneven_batch"] = uneven_batch(dev, pinned=pinned_many)
         torch.cuda.empty_cache()
     if not args.no_multi_qpu:
         progress("multi-QPU n = 32")

@@ -15,6 +15,8 @@
 // MIX butterflies of the backward sweep.  All accumulations are FP64 and are
 // reduced in a fixed order (no floating-point atomics), so results are
 // bit-reproducible.
+#include <type_traits>
+
 #include "qq_device.h"
 
 namespace qq {
@@ -290,40 +292,55 @@ constexpr int kMaxPairs = QQ_MAX_N * (QQ_MAX_N - 1) / 2;
 // One thread per basis index z.  Real problems: FP64 sum in the canonical order
 // (c0, then l_i for ascending i, then b_ij row-major) over the set bits of z;
 // integer problems: exact int32 sum of the same terms.
-template <bool INT, typename DT>
+template <bool INT, typename DT, typename Z>
 __global__ void __launch_bounds__(256) cost_diag_kernel(int n, uint64_t dim, const double *ell, const int32_t *ell_i,
                                                          int npairs, const int32_t *pij, const double *pb,
                                                          const int32_t *pbi, double c0, int32_t c0_i, DT *out)
 {
-    __shared__ double s_ell[QQ_MAX_N];
-    __shared__ int32_t s_elli[QQ_MAX_N];
-    __shared__ uint8_t s_i[kMaxPairs], s_j[kMaxPairs];
-    __shared__ double s_b[kMaxPairs];
-    __shared__ int32_t s_bi[kMaxPairs];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        if (INT) s_elli[k] = ell_i[k];
-        else s_ell[k] = ell[k];
-    }
-    for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
-        s_i[k] = (uint8_t)pij[2 * k];
-        s_j[k] = (uint8_t)pij[2 * k + 1];
-        if (INT) s_bi[k] = pbi[k];
-        else s_b[k] = pb[k];
-    }
-    __syncthreads();
+    // Every coefficient index is wave-uniform, so the coefficients come through the scalar cache; each
+    // thread carries kPer indices through the same coefficient loop (one coefficient load serves them
+    // all).  The additions for one index are taken in the canonical order (c0, l_i ascending, b_ij
+    // row-major), adding a term only where its bits are set, so the FP64 entries equal the one-index
+    // sums bit for bit.  Z: 32-bit indices while 2^n fits, 64-bit beyond.
+    constexpr int kPer = 4;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < dim; z += stride) {
-        if constexpr (INT) {
-            int32_t acc = c0_i;
-            for (int i = 0; i < n; ++i) acc += ((z >> i) & 1) ? s_elli[i] : 0;
-            for (int k = 0; k < npairs; ++k) acc += (((z >> s_i[k]) & (z >> s_j[k])) & 1) ? s_bi[k] : 0;
-            out[z] = (DT)acc;
-        } else {
-            double acc = c0;
-            for (int i = 0; i < n; ++i) acc = ((z >> i) & 1) ? acc + s_ell[i] : acc;
-            for (int k = 0; k < npairs; ++k) acc = (((z >> s_i[k]) & (z >> s_j[k])) & 1) ? acc + s_b[k] : acc;
-            out[z] = (DT)acc;
+    for (uint64_t z0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z0 < dim; z0 += stride * kPer) {
+        Z z[kPer];
+        typename std::conditional<INT, int32_t, double>::type acc[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            z[u] = (Z)(z0 + u * stride);
+            if constexpr (INT) acc[u] = c0_i;
+            else acc[u] = c0;
         }
+        for (int i = 0; i < n; ++i) {
+            const int iu = __builtin_amdgcn_readfirstlane(i);
+            if constexpr (INT) {
+                const int32_t l = ell_i[iu];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) acc[u] += ((z[u] >> iu) & 1) ? l : 0;
+            } else {
+                const double l = ell[iu];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) acc[u] = ((z[u] >> iu) & 1) ? acc[u] + l : acc[u];
+            }
+        }
+        for (int k = 0; k < npairs; ++k) {
+            const int ku = __builtin_amdgcn_readfirstlane(k);
+            const int a = pij[2 * ku], b = pij[2 * ku + 1];
+            if constexpr (INT) {
+                const int32_t w = pbi[ku];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) acc[u] += ((z[u] >> a) & (z[u] >> b) & 1) ? w : 0;
+            } else {
+                const double w = pb[ku];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) acc[u] = ((z[u] >> a) & (z[u] >> b) & 1) ? acc[u] + w : acc[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (z0 + u * stride < dim) out[z0 + u * stride] = (DT)acc[u];
     }
 }
 
@@ -514,32 +531,78 @@ __device__ void tournament(TopList &L, int k, double *outp, uint64_t *outi)
     }
 }
 
+// Stage 1 of the top-k: the best k (probability, index) pairs of each workgroup's amplitudes.  Each
+// wave keeps its own best k in registers spread over its lanes (lane j holds the j-th best, in the
+// order of `better`), and an amplitude is a candidate only if it beats the wave's current k-th best.
+// A wave sees its amplitudes in an order unrelated to their probabilities, so after the first few
+// chunks candidates are rare: most of the sweep is a load, |psi|^2 and one comparison per amplitude,
+// and the insertions (a wave-uniform loop over the ballot of candidates) are taken one at a time.
 template <typename C2>
 __global__ void __launch_bounds__(256) topk_stage1(const C2 *psi, uint64_t dim, int k, double *cp, uint64_t *ci)
 {
-    TopList L;
-    L.init();
-    // kUnroll coalesced loads in flight per thread before the insertions (the ranking by
-    // (probability, index) does not depend on the insertion order)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double lp = -1.0;      // this lane's entry of the wave's list (j-th best for lane j < k)
+    uint64_t li = ~0ull;
+    double tp = -1.0;      // the wave's current k-th best (wave-uniform)
+    uint64_t ti = ~0ull;
     constexpr int kUnroll = 8;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t z0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z0 < dim; z0 += stride * kUnroll) {
+    // the loop runs over wave-uniform bases so that every lane takes part in the ballots and shuffles
+    for (uint64_t zb = (uint64_t)blockIdx.x * blockDim.x + (uint64_t)wave * 64; zb < dim; zb += stride * kUnroll) {
         C2 v[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t z = z0 + u * stride;
+            const uint64_t z = zb + lane + u * stride;
             if (z < dim) v[u] = psi[z];
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t z = z0 + u * stride;
-            if (z < dim) {
-                const double re = (double)v[u].x, im = (double)v[u].y;
-                L.insert(fma(re, re, im * im), z);
+            const uint64_t z = zb + lane + u * stride;
+            const bool valid = z < dim;
+            const double re = valid ? (double)v[u].x : 0.0, im = valid ? (double)v[u].y : 0.0;
+            const double pz = valid ? fma(re, re, im * im) : -1.0;
+            uint64_t m = __ballot(valid && better(pz, z, tp, ti));
+            while (m) {
+                const int src = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const double xp = __shfl(pz, src);
+                const uint64_t xi = __shfl(z, src);
+                if (!better(xp, xi, tp, ti)) continue;  // overtaken by an insertion of this chunk
+                const int pos = __popcll(__ballot(lane < k && better(lp, li, xp, xi)));
+                const double up = __shfl_up(lp, 1);
+                const uint64_t ui = __shfl_up(li, 1);
+                if (lane == pos) {
+                    lp = xp;
+                    li = xi;
+                } else if (lane > pos) {
+                    lp = up;
+                    li = ui;
+                }
+                tp = __shfl(lp, k - 1);
+                ti = __shfl(li, k - 1);
             }
         }
     }
-    tournament(L, k, cp + (size_t)blockIdx.x * k, ci + (size_t)blockIdx.x * k);
+    // the workgroup's best k from the four wave lists: each candidate's rank is the number of
+    // candidates better than it (ties between empty entries broken by position, so ranks are distinct)
+    __shared__ double sp[4 * kTopK];
+    __shared__ uint64_t si[4 * kTopK];
+    if (lane < k) {
+        sp[wave * k + lane] = lp;
+        si[wave * k + lane] = li;
+    }
+    __syncthreads();
+    if (wave == 0 && lane < 4 * k) {
+        const double mp = sp[lane];
+        const uint64_t mi = si[lane];
+        int rank = 0;
+        for (int j = 0; j < 4 * k; ++j)
+            rank += (better(sp[j], si[j], mp, mi) || (j < lane && sp[j] == mp && si[j] == mi)) ? 1 : 0;
+        if (rank < k) {
+            cp[(size_t)blockIdx.x * k + rank] = mp;
+            ci[(size_t)blockIdx.x * k + rank] = mi;
+        }
+    }
 }
 
 template <typename DT>
@@ -598,21 +661,26 @@ hipError_t launch_cost_diag(int n, int diag_type, const double *d_ell, const int
                             const int32_t *d_pair_ij, const double *d_pair_b, const int32_t *d_pair_bi, double c0,
                             int32_t c0_i, void *d_out, uint64_t dim, hipStream_t s)
 {
-    const dim3 grid(grid_for(dim, 65536)), block(256);
+    const dim3 grid(grid_for((dim + 3) / 4, 65536)), block(256);
+    const bool z32 = dim <= (1ull << 32);
+#define QQ_COST_DIAG(INT, DT, Z)                                                                                  \
+    hipLaunchKernelGGL((cost_diag_kernel<INT, DT, Z>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs, d_pair_ij, \
+                       d_pair_b, d_pair_bi, c0, c0_i, static_cast<DT *>(d_out))
     switch (diag_type) {
     case DIAG_F64:
-        hipLaunchKernelGGL((cost_diag_kernel<false, double>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs,
-                           d_pair_ij, d_pair_b, d_pair_bi, c0, c0_i, static_cast<double *>(d_out));
+        if (z32) QQ_COST_DIAG(false, double, uint32_t);
+        else QQ_COST_DIAG(false, double, uint64_t);
         break;
     case DIAG_I32:
-        hipLaunchKernelGGL((cost_diag_kernel<true, int32_t>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs,
-                           d_pair_ij, d_pair_b, d_pair_bi, c0, c0_i, static_cast<int32_t *>(d_out));
+        if (z32) QQ_COST_DIAG(true, int32_t, uint32_t);
+        else QQ_COST_DIAG(true, int32_t, uint64_t);
         break;
     default:
-        hipLaunchKernelGGL((cost_diag_kernel<true, int16_t>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs,
-                           d_pair_ij, d_pair_b, d_pair_bi, c0, c0_i, static_cast<int16_t *>(d_out));
+        if (z32) QQ_COST_DIAG(true, int16_t, uint32_t);
+        else QQ_COST_DIAG(true, int16_t, uint64_t);
         break;
     }
+#undef QQ_COST_DIAG
     return hipGetLastError();
 }
 
