@@ -908,17 +908,24 @@ def main():
         progress("plain per-gate comparator")
         pb.evaluate_plain(x[0], grad=True)  # warm-up (its allocations and first launches)
         torch.cuda.synchronize()
-        times = []
+        times, dev_ms = [], []
         for _ in range(3):
+            N.qq_profile_enable(True)
+            N.qq_profile_read()
             t0 = time.perf_counter()
             pb.evaluate_plain(x[0], grad=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+            N.qq_profile_enable(False)
+            dev_ms += [r["ms"] for r in N.qq_profile_read() if r["kind"] == 9]
         tp = float(np.median(times))
         out["plain_fp64"] = {"evals_per_s": round(1.0 / tp, 4), "seconds_per_eval": round(tp, 3),
                              "seconds_all": [round(t, 3) for t in times], "speedup": round(value * tp, 2),
+                             "device_seconds_per_eval": round(float(np.median(dev_ms)) / 1e3, 3) if dev_ms else None,
+                             "speedup_device": round(value * float(np.median(dev_ms)) / 1e3, 2) if dev_ms else None,
                              "timing": "one warm-up, then the median of three calls (each call allocates and "
-                                       "frees its own complex128 states)",
+                                       "frees its own complex128 states); device_seconds_per_eval: HIP events around "
+                                       "the call's launch sequence alone, without its allocation",
                              "definition": "complex128, one kernel per gate (phase per layer, RX per qubit and "
                                            "layer, energy reduction, unfused adjoint), one parameter set per call"}
     pb.close()

@@ -603,7 +603,8 @@ qq_status qq_evaluate_plain(qq_problem *prob, int p, const double *params, int f
 typedef struct {
     int kind;       /* 1: forward pass (one state), 2: adjoint pass (psi and lambda), 3: final reduction,
                        4: persistent many-problem launch, 5: cost diagonal, 6: min/max of C,
-                       7: probabilities, 8: top-k */
+                       7: probabilities, 8: top-k, 9: the whole launch sequence of one qq_evaluate_plain call
+                       (bytes 0) */
     int pass_kind;  /* complex64 specialised kernel: 0 first, 1 mid, 2 turn, 3 last, 4 last+adjoint seed,
                        5 adjoint mid, 6 adjoint turn, 7 adjoint last; -1: generic pass kernel */
     int high;       /* 1 when the pass mixes qubits above 11 (strided tile) */

@@ -2626,7 +2626,8 @@ qq_status qq_evaluate_plain(qq_problem *pb, int p, const double *params, int fla
     a.partial = reinterpret_cast<double *>(ws + align_up(state) * (grad ? 2 : 1));
     a.result = reinterpret_cast<double *>(ws + align_up(state) * (grad ? 2 : 1) + align_up(sizeof(double) * nblocks));
     a.nblocks = nblocks;
-    QQ_HIP(run_plain(a, stream));
+    // profiled as one record: the whole per-gate launch sequence, without the allocation and the copy-out
+    QQ_HIP(prof_aux(9, pb->n, diag_bytes_of(pb->diag_type), 0.0, stream, [&]() { return run_plain(a, stream); }));
     std::vector<double> h(1 + 2 * p);
     QQ_HIP(hipMemcpyAsync(h.data(), a.result, sizeof(double) * h.size(), hipMemcpyDeviceToHost, stream));
     QQ_HIP(hipStreamSynchronize(stream));

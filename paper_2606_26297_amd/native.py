@@ -690,7 +690,8 @@ def qq_profile_read(max_records: int = 1 << 16):
 
 PASS_KIND_NAMES = ["FK_FIRST", "FK_MID", "FK_TURN", "FK_LAST", "FK_LASTG", "FK_BMID", "FK_BTURN", "FK_BLAST"]
 DIAG_TYPE_NAMES = {8: "double", 4: "int", 2: "short"}
-AUX_KIND_NAMES = {5: "cost_diag_kernel", 6: "minmax_kernel", 7: "prob_kernel", 8: "topk_stage1+2"}
+AUX_KIND_NAMES = {5: "cost_diag_kernel", 6: "minmax_kernel", 7: "prob_kernel", 8: "topk_stage1+2",
+                  9: "plain_per_gate_sequence"}
 
 
 def kernel_name(rec) -> str:

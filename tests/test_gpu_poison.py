@@ -70,3 +70,19 @@ def test_call_log_line(capfd, monkeypatch):
     finally:
         pb.close()
         os.environ.pop("QQ_LOG", None)
+
+
+def test_poisoned_static_workspace_changes_nothing(monkeypatch):
+    """The allocation-free entry point under QQ_POISON: its fixed array is filled with NaN words before
+    each call's kernels, and the results still equal the unpoisoned qq_evaluate ones bit for bit."""
+    inst = W.dense_gaussian_upper(16, 506)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    try:
+        x = W.random_params(2, 3, 507)
+        e_r, g_r = pb.evaluate(x, grad=True)
+        monkeypatch.setenv("QQ_POISON", "1")
+        e, g = np.empty(3), np.empty((3, 4))
+        N.qq_evaluate_static(pb.handle, 2, 3, x, N.QQ_ENERGY | N.QQ_GRAD, None, e, g)
+        assert np.array_equal(e, e_r) and np.array_equal(g, g_r)
+    finally:
+        pb.close()

@@ -110,3 +110,17 @@ def test_static_rejects_bad_arguments_like_evaluate():
     e = np.zeros(1)
     assert L.qq_evaluate_static(None, 1, 1, x.ctypes.data_as(dp), N.QQ_ENERGY, None, e.ctypes.data_as(dp),
                                 None) == N.QQ_E_INVALID
+
+
+def test_static_complex128_and_partitioned():
+    inst = W.dense_integer_symmetric(13, 909)
+    pb = Problem(inst.H, inst.f, inst.c0)
+    try:
+        pb.set_allocation(W.contiguous_allocation(13, [7, 6]), 2, [7, 6])
+        x = W.random_params(2, 2, 910)
+        for flags in (N.QQ_ENERGY | N.QQ_GRAD | N.QQ_C128, N.QQ_ENERGY | N.QQ_GRAD | N.QQ_PARTITIONED):
+            e_s, g_s = static(pb, x, flags)
+            e_r, g_r = reference(pb, x, flags)
+            assert np.array_equal(e_s, e_r) and np.array_equal(g_s, g_r), flags
+    finally:
+        pb.close()
