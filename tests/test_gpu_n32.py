@@ -11,8 +11,9 @@ any size (1e-5 relative; energy |dE| / max(|E|, sigma_C), gradient
     contiguous allocation, p = 2, two parameter sets): the partitioned energy,
     gradient and final state against the monolithic ones (the state compared on
     the device, ||psi_part - psi_mono||_2 <= 1e-5), and the complex64 energy and
-    gradient against the complex128 generic kernel, and 2000 sampled entries of its
-    cost diagonal against the oracle's one-index sums (bit for bit).
+    gradient against the complex128 generic kernel and against central differences of
+    complex128 energies (forward path only), and 2000 sampled entries of its cost
+    diagonal against the oracle's one-index sums (bit for bit).
 Device memory: the diagonal and the cross diagonal (FP64, 32 GiB each) plus the
 states of the evaluation; at most about 160 GiB at once.
 """
@@ -186,5 +187,38 @@ def test_n32_dense_cost_diagonal_sampled_against_the_oracle():
         ell, b = O.canonicalise(inst.H, inst.f)
         want = np.array([O.cost_at_real(ell, b, inst.c0, int(z)) for z in zs])
         assert np.array_equal(got, want), int(np.sum(got != want))
+    finally:
+        pb.close()
+
+
+def test_n32_dense_gradient_vs_central_differences():
+    """The dense n = 32 multi-QPU workload (496 couplings, p = 2): the complex64 adjoint gradient, monolithic
+    and partitioned, against five-point central differences of complex128 energies, which use the forward
+    path only (the FP64 oracle needs 160 GiB of host memory and about an hour at this size).  The gradient
+    here is small (||g||_inf about 2e-4 sigma_C), so the stencil is the fourth-order one with h = 1e-3:
+    its truncation (h^4 / 30 times the fifth derivative) and the complex128 energies' rounding divided by
+    h both stay near 1e-10, far below the bar of 1e-5 relative to ||g||_inf."""
+    inst, x, alloc = W.workload5()
+    pb = Problem(inst.H, inst.f, inst.c0)
+    try:
+        pb.set_allocation(alloc, 4, O.balanced_capacities(N32, 4))
+        x0 = x[:1]
+        print("complex64 gradients", flush=True)
+        _, g_mono = pb.evaluate(x0, grad=True)
+        _, g_part = pb.evaluate(x0, grad=True, partitioned=True)
+        h = 1e-3
+        fd = np.empty(4)
+        for j in range(4):
+            e = []
+            for steps in ((2, 1), (-1, -2)):  # two complex128 states at a time: 128 GiB
+                xs = np.repeat(x0, 2, axis=0)
+                xs[0, j] += steps[0] * h
+                xs[1, j] += steps[1] * h
+                print(f"complex128 energies, component {j}, offsets {steps}", flush=True)
+                e.extend(pb.evaluate(xs, c128=True))
+            fd[j] = (-e[0] + 8 * e[1] - 8 * e[2] + e[3]) / (12 * h)
+        print(f"fd {fd} adjoint {g_mono[0]}", flush=True)
+        assert g_rel(g_mono, fd) <= 1e-5, (g_mono, fd)
+        assert g_rel(g_part, fd) <= 1e-5, (g_part, fd)
     finally:
         pb.close()
