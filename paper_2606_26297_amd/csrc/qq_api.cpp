@@ -182,11 +182,21 @@ struct qq_problem {
     // graphs captured on this problem: they hold its device pointers, so the problem is not
     // destroyed and its allocation not replaced while any exists
     int graphs = 0;
+    // Per-tile cost tables of the complex64 per-pass kernels (launch_cost_table), in one allocation: one
+    // per tile geometry (high, pos4, pos8) of every set plan and per cost layout (the tile's lane and wave
+    // qubits at lane_q, its register qubits at the other run); each is [tiles][kCostRow] rows followed
+    // by the per-thread constants [256][8].  Built once at creation, so no evaluation allocates for them.
+    struct CostTab {
+        int high, pos4, pos8, lane_q;
+        size_t off;  // in doubles from d_ctab
+    };
+    std::vector<CostTab> ctabs;
+    double *d_ctab = nullptr;
 
     ~qq_problem()
     {
         void *ptrs[] = {d_diag, d_ell, d_ell_i, d_pair_ij, d_pair_b, d_pair_bi, d_regq, d_part_cq, d_qpu, d_tables, d_cross,
-                        d_part};
+                        d_part, d_ctab};
         if (dim) (void)hipSetDevice(device);
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
@@ -560,16 +570,81 @@ double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128, bo
             diag_reads += 1;
         if ((o.kind == OP_PHASE || (o.kind == OP_GGAMMA && (o.flags & OPF_UNPHASE))) && part) cross_reads += 1;
     }
-    // the specialised kernels read 5 of every 16 diagonal (and cross-diagonal) entries and form the
-    // rest from them
+    // the specialised kernels read one cost-table row per tile of 4096 entries in place of the cost
+    // diagonal, and 5 of every 16 cross-diagonal entries, forming the rest from them
     if (fast) {
-        diag_reads *= 5.0 / 16.0;
+        diag_reads *= kCostRow * sizeof(double) / (4096.0 * d);
         cross_reads *= 5.0 / 16.0;
     }
     return (double)pb->dim * (B * moves * es + (diag_reads + cross_reads) * d);
 }
 
 // Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
+// The per-tile cost tables of a problem (see qq_problem::CostTab): the rows on the device, the
+// per-thread constants (P(E) and l_Rj + sum_{q in E} b_q,Rj, with E the thread's lane and wave bits) on
+// the host from the canonical coefficients.
+qq_status build_cost_tables(qq_problem *pb, hipStream_t stream)
+{
+    const int n = pb->n;
+    if (n <= kTileBits || n > kFastMaxN) return QQ_OK;
+    const uint64_t T = tiles_per_state(n);
+    std::vector<qq_problem::CostTab> tabs;
+    auto add = [&](const SetDesc &sd, int lane_q) {
+        for (const auto &t : tabs)
+            if (t.high == sd.high && t.pos4 == sd.pos4 && t.pos8 == sd.pos8 && t.lane_q == lane_q) return;
+        tabs.push_back({sd.high, sd.pos4, sd.pos8, lane_q, 0});
+    };
+    for (int pr = 0; pr < (pairing_applies(n) ? 3 : 1); ++pr)
+        for (const SetDesc &sd : make_sets(n, pr)) {
+            add(sd, sd.pos4);
+            add(sd, sd.pos8);
+        }
+    const size_t per = (size_t)T * kCostRow + 256 * 8;
+    if (hipMalloc((void **)&pb->d_ctab, per * tabs.size() * sizeof(double)) != hipSuccess)
+        return fail(QQ_E_NOMEM, "hipMalloc(%zu) for the cost tables failed", per * tabs.size() * sizeof(double));
+    auto B = [&](int i, int j) { return i < j ? pb->b[(size_t)i * n + j] : pb->b[(size_t)j * n + i]; };
+    std::vector<double> thr(256 * 8 * tabs.size(), 0.0);
+    const int np = (int)pb->pair_b.size();
+    for (size_t k = 0; k < tabs.size(); ++k) {
+        qq_problem::CostTab &tb = tabs[k];
+        tb.off = k * per;
+        const int lq = tb.lane_q, rq = lq == tb.pos4 ? tb.pos8 : tb.pos4;
+        QQ_HIP(launch_cost_table(n, tb.high, tb.pos4, tb.pos8, lq, rq, T, pb->d_ell, np, pb->d_pair_ij, pb->d_pair_b,
+                                 pb->c0, pb->d_ctab + tb.off, stream));
+        const int eq[8] = {0, 1, 2, 3, lq, lq + 1, lq + 2, lq + 3};
+        for (int t = 0; t < 256; ++t) {
+            double P = 0.0;
+            for (int a = 0; a < 8; ++a) {
+                if (!((t >> a) & 1)) continue;
+                P += pb->ell[eq[a]];
+                for (int c = a + 1; c < 8; ++c)
+                    if ((t >> c) & 1) P += B(eq[a], eq[c]);
+            }
+            double *row = &thr[(k * 256 + t) * 8];
+            row[0] = P;
+            for (int j = 0; j < 4; ++j) {
+                double q = pb->ell[rq + j];
+                for (int a = 0; a < 8; ++a)
+                    if ((t >> a) & 1) q += B(eq[a], rq + j);
+                row[1 + j] = q;
+            }
+        }
+    }
+    for (size_t k = 0; k < tabs.size(); ++k)
+        QQ_HIP(hipMemcpyAsync(pb->d_ctab + tabs[k].off + (size_t)T * kCostRow, &thr[k * 256 * 8], 256 * 8 * sizeof(double),
+                              hipMemcpyHostToDevice, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    pb->ctabs = tabs;
+    return QQ_OK;
+}
+
+const double *find_cost_table(const qq_problem *pb, const SetDesc &sd, int lane_q)
+{
+    for (const auto &t : pb->ctabs)
+        if (t.high == sd.high && t.pos4 == sd.pos4 && t.pos8 == sd.pos8 && t.lane_q == lane_q) return pb->d_ctab + t.off;
+    return nullptr;
+}
+
 qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int B, int flags, char *ws,
                    const double *d_params, hipStream_t stream, bool capturing = false)
 {
@@ -652,6 +727,10 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             fp.part_cq = pb->d_part_cq;
             fp.part_cq_runs = std::max(1, pb->n - 3);
             fp.shift = pb->alpha;
+            // the table of the layout the pass reads the cost in: lanes at pos4 for the first pass, at pos8 else
+            fp.ctab = find_cost_table(pb, sd, pp.fkind == FK_FIRST ? sd.pos4 : sd.pos8);
+            if (!fp.ctab) return fail(QQ_E_DEVICE, "no cost table for the set at qubits %d / %d", sd.pos4, sd.pos8);
+            fp.cthr = fp.ctab + (size_t)T * kCostRow;
             QQ_HIP(launch_fast_pass(pp.fkind, sd.high != 0, pb->diag_type, fp, stream));
         } else {
             QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
@@ -1056,6 +1135,9 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
                     P.store_psi = (pp.flags & PF_STORE_PSI) ? 1 : 0;
                     P.slot_base = slot_base;
                     P.nslots = (int)pp.slot_out.size();
+                    P.ctab = find_cost_table(pb, sd, pp.fkind == FK_FIRST ? sd.pos4 : sd.pos8);
+                    if (!P.ctab) return fail(QQ_E_DEVICE, "no cost table for the set at qubits %d / %d", sd.pos4, sd.pos8);
+                    P.cthr = P.ctab + (size_t)I.tiles * kCostRow;
                     slot_base += P.nslots;
                     for (int o : pp.slot_out) G.slot_out.push_back((uint16_t)o);
                     G.pass.push_back(P);
@@ -1330,6 +1412,7 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
         return launch_cost_diag(n, pb->diag_type, pb->d_ell, pb->d_ell_i, np, pb->d_pair_ij, pb->d_pair_b,
                                 pb->d_pair_bi, c0, pb->c0_i, pb->d_diag, pb->dim, stream);
     }));
+    if (qq_status st = build_cost_tables(pb, stream); st != QQ_OK) return st;
 
     // min / argmin / max of C
     const int nblk = (int)std::min<uint64_t>(1024, (pb->dim + 255) / 256);

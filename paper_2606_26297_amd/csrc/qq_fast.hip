@@ -20,7 +20,8 @@ __device__ __forceinline__ void fast_pass_impl(const FastArgs &a)
     int b, g;
     block_coords(a.B, a.G, b, g);
     double acc[3] = {0.0, 0.0, 0.0};
-    run_pass<KIND, HIGH, FULL, DT, PART, WIDE>(a, lds, acc, t, b, g);
+    // the per-pass kernels form the cost values from the per-tile tables (non-partitioned phases)
+    run_pass<KIND, HIGH, FULL, DT, PART, WIDE, !PART>(a, lds, acc, t, b, g);
 
     if constexpr (NSLOT > 0) {
         const int lane = t & 63, wave = t >> 6;
@@ -168,6 +169,8 @@ hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassPa
     a.pcq = pp.part_cq;
     a.pcq_runs = pp.part_cq_runs;
     a.shift = pp.shift;
+    a.ctab = pp.ctab;
+    a.cthr = pp.cthr;
     const bool part = pp.part != 0;
     switch (kind) {
     case FK_FIRST: return launch_kind<FK_FIRST>(a, high, diag_type, part, s);

@@ -157,8 +157,27 @@ struct FastPassParams {
     const double *part_cq;
     int part_cq_runs;
     double shift;  // centre of the cost for the accumulations (the mean of C)
+    // per-tile cost table of the layout in which the pass reads the cost ([tiles][kCostRow]) and the
+    // per-thread constants ([256][8]) that follow it; required by every non-partitioned pass kind that
+    // reads the cost
+    const double *ctab;
+    const double *cthr;
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
+
+// Per-tile cost table of one tile geometry and layout (qq_kernels.hip).  A tile's 4096 states are
+// z = T + E + R: T its base bits, E the thread's bits (qubits 0..3 and the two lane qubits at lane_q:
+// the lane l = t & 63; the two wave qubits at lane_q + 2: the wave w = t >> 6), R the register bits
+// (the four qubits at reg_q).  Row r of tile r (kCostRow doubles):
+//   [l]      C(T) + sum over the lane bits q of l of G_q(T)     (l = 0..63)
+//   [64 + w] sum over the wave bits q of w of G_q(T)            (w = 0..3)
+//   [68 + j] G_{reg_q + j}(T)                                    (j = 0..3)
+// with G_q(T) = sum_{i in T} b_iq and C(T) the cost of the base bits alone (c0 included).
+// high: tile bases as in the strided high tiles (tile_base with pos4, pos8), else tile << 12.
+constexpr int kCostRow = 72;
+hipError_t launch_cost_table(int n, int high, int pos4, int pos8, int lane_q, int reg_q, uint64_t tiles,
+                             const double *d_ell, int npairs, const int32_t *d_pair_ij, const double *d_pair_b,
+                             double c0, double *out, hipStream_t s);
 
 // Device address of the fixed scratch array (QQ_STATIC_SCRATCH_BYTES) on `device`, taken once per
 // device with hipGetSymbolAddress (qq_static.hip).
@@ -191,6 +210,8 @@ struct ManyPass {
     int kind, k, geom;      // geom 0: qubits 0..11; 1: high set, all 8 bits active; 2: high set, partial
     int pos4, pos8, w1, w2, active, nact, store_psi;
     int slot_base, nslots;  // first accumulator slot of the pass inside its problem
+    const double *ctab;     // the cost table of the pass's layout and its per-thread constants
+    const double *cthr;
 };
 struct ManySeg {
     uint32_t first;  // ticket of chunk 0

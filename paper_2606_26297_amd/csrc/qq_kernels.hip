@@ -657,6 +657,76 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+namespace {
+
+// One row per tile (layout with launch_cost_table's declaration): C(T) of the tile's base bits T
+// (c0, then l_i over T, then the couplings inside T) and G_q(T) = sum_{i in T} b_iq for the tile's
+// 12 qubits, combined into the per-lane, per-wave and per-register entries.
+__global__ void __launch_bounds__(256) cost_table_kernel(int n, int high, int pos4, int pos8, int lane_q, int reg_q,
+                                                          uint64_t tiles, const double *ell, int npairs,
+                                                          const int32_t *pij, const double *pb, double c0,
+                                                          double *out)
+{
+    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= tiles) return;
+    const uint64_t T = high ? tile_base(tile, pos4, pos8, pos4 - 4, pos8 - pos4 - 4) : (tile << kTileBits);
+    // slots 0..3: qubits 0..3, 4..7: lane_q .. lane_q + 3, 8..11: reg_q .. reg_q + 3
+    auto slot = [&](int q) {
+        if (q < 4) return q;
+        if (q >= lane_q && q < lane_q + 4) return 4 + (q - lane_q);
+        if (q >= reg_q && q < reg_q + 4) return 8 + (q - reg_q);
+        return -1;
+    };
+    double C = c0;
+    for (int i = 0; i < n; ++i)
+        if ((T >> i) & 1ull) C += ell[i];
+    double G[12];
+#pragma unroll
+    for (int s = 0; s < 12; ++s) G[s] = 0.0;
+    for (int k = 0; k < npairs; ++k) {
+        const int i = pij[2 * k], j = pij[2 * k + 1];
+        const double w = pb[k];
+        const int si = slot(i), sj = slot(j);
+        const bool bi = (T >> i) & 1ull, bj = (T >> j) & 1ull;
+        if (si < 0 && sj < 0) {
+            if (bi && bj) C += w;
+        } else if (si < 0 || sj < 0) {
+            // one end on the tile, the other in the base bits
+            const int s = si < 0 ? sj : si;
+            const bool on = si < 0 ? bi : bj;
+#pragma unroll
+            for (int u = 0; u < 12; ++u)
+                if (u == s && on) G[u] += w;
+        }
+    }
+    double *row = out + tile * kCostRow;
+    for (int l = 0; l < 64; ++l) {
+        double z = C;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            if ((l >> q) & 1) z += G[q];
+        row[l] = z;
+    }
+    row[64] = 0.0;
+    row[65] = G[6];
+    row[66] = G[7];
+    row[67] = G[6] + G[7];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) row[68 + j] = G[8 + j];
+}
+
+}  // namespace
+
+hipError_t launch_cost_table(int n, int high, int pos4, int pos8, int lane_q, int reg_q, uint64_t tiles,
+                             const double *d_ell, int npairs, const int32_t *d_pair_ij, const double *d_pair_b,
+                             double c0, double *out, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((tiles + 255) / 256);
+    hipLaunchKernelGGL(cost_table_kernel, dim3(grid), dim3(256), 0, s, n, high, pos4, pos8, lane_q, reg_q, tiles,
+                       d_ell, npairs, d_pair_ij, d_pair_b, c0, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_cost_diag(int n, int diag_type, const double *d_ell, const int32_t *d_ell_i, int npairs,
                             const int32_t *d_pair_ij, const double *d_pair_b, const int32_t *d_pair_bi, double c0,
                             int32_t c0_i, void *d_out, uint64_t dim, hipStream_t s)

@@ -112,6 +112,47 @@ __device__ __forceinline__ double reg_cost(RegCost &c, RegQ *cq, int r)
     return c.v[r];
 }
 
+// Cost values of a thread's 16 registers from the pass's per-tile table, without reading the cost
+// diagonal.  C is quadratic (eq. (6)): with z0 = T + E, T the tile's base bits and E the thread's own
+// bits (qubits 0..3, two lane and two wave qubits, in the order of the thread index t),
+//   C(z0) = C(T) + P(E) + sum_{q in E} G_q(T),   G_q(T) = sum_{i in T} b_iq,
+//   P(E) = sum_{j in E} l_j + sum_{j<k in E} b_jk,
+// and the increment of register qubit R_j is C(z0 + 2^R_j) - C(z0) = G_Rj(T) + l_Rj + sum_{q in E} b_q,Rj.
+// The table row holds C(T) plus the lane bits' sum per lane, the wave bits' sum per wave and the four
+// G_Rj(T); the thread's P(E) and l_Rj + sum_{q in E} b_q,Rj are per-thread constants (thr, 8 doubles).
+// Exact for integer costs; for real ones within a few units in the last place of the diagonal's
+// canonical sums.
+// The values one tile's formation reads: the lane's and the wave's entries and the four register
+// increments of the row (wave-uniform, read through the constant address space so they take scalar
+// loads), the thread's five constants.
+struct TabVals {
+    double lane, wave, reg[4], thr[5];
+};
+
+using cdouble_t = const __attribute__((address_space(4))) double;
+
+__device__ __forceinline__ void tab_load(TabVals &tv, const double *row, const double *thr, int t, uint32_t wave)
+{
+    cdouble_t *u = (cdouble_t *)row;
+    tv.lane = row[t & 63];
+    tv.wave = u[64 + wave];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tv.reg[j] = u[68 + j];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) tv.thr[j] = thr[j];
+}
+
+__device__ __forceinline__ void reg_cost_form(RegCost &c, const TabVals &tv)
+{
+    const double z = (tv.lane + tv.wave) + tv.thr[0];
+    c.v[0] = z;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        c.k[j] = tv.reg[j] + tv.thr[1 + j];
+        c.v[1 << j] = z + c.k[j];
+    }
+}
+
 struct MixCoef {
     float m;      // t (form A) or u (form B), direction folded in
     int formB;
@@ -399,6 +440,11 @@ struct FastArgs {
     // the energy.
     double shift;
     int pcq_runs;          // run starts per factor (n - 3)
+    // Cost table of the layout in which the pass reads the cost: ctab[tile][kCostRow] (per-lane,
+    // per-wave and per-register parts of the tile's base-bit sums, see launch_cost_table) and
+    // cthr[thread][8], the thread's own part (see reg_cost_form).
+    const double *ctab;
+    const double *cthr;
 };
 
 // ---- partitioned phase (eq. (16)) --------------------------------------------------------------
@@ -538,11 +584,13 @@ constexpr int kind_slots()
 }
 
 // The tile loop of one pass kind.  FB1 / FB2: form of the first / second mixer coefficient.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool WIDE, bool FB1, bool FB2>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool WIDE, bool FB1, bool FB2, bool CT>
 __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g,
                                           const MixCoef &c1, const MixCoef &c2, double g2pi)
 {
     constexpr int NS = kind_states<KIND>();
+    // CT: cost values from the per-tile tables (passes that read the cost, non-partitioned phases)
+    constexpr bool TAB = CT && !PART && KIND != FK_MID && KIND != FK_BMID;
     // Global addressing.  Tile-local bits 0..3 and the two lane bits above them
     // vary per thread (a 32-bit byte offset); the two wave bits and the four
     // register bits are wave-uniform and go into a 64-bit scalar base per register.
@@ -580,9 +628,21 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         const uint64_t rs2 = opaque_u64(1ull << a.pos8), rs1 = opaque_u64(1ull << a.pos4);
         const uint64_t b2 = base + w2, b1 = base + w1;
         RegQ *cq = (RegQ *)a.cq;
-        // cost values of the thread's registers in layout 2 / layout 1 (five loads each)
-        auto cz2 = [&](RegCost &rc) { reg_cost_load<DT>(rc, diag_a, b2, rs2, vd2); };
-        auto cz1 = [&](RegCost &rc) { reg_cost_load<DT>(rc, diag_a, b1, rs1, vd1); };
+        // cost values of the thread's registers in layout 2 / layout 1: five loads of the diagonal, or
+        // (TAB) the load of the tile's table row, with the values formed by cz_ready before their use
+        TabVals tv;
+        auto tab_issue = [&]() { tab_load(tv, a.ctab + tile * kCostRow, a.cthr + 8 * t, t, wave); };
+        auto cz2 = [&](RegCost &rc) {
+            if constexpr (TAB) tab_issue();
+            else reg_cost_load<DT>(rc, diag_a, b2, rs2, vd2);
+        };
+        auto cz1 = [&](RegCost &rc) {
+            if constexpr (TAB) tab_issue();
+            else reg_cost_load<DT>(rc, diag_a, b1, rs1, vd1);
+        };
+        auto cz_ready = [&](RegCost &rc) {
+            if constexpr (TAB) reg_cost_form(rc, tv);
+        };
         auto ld2 = [&](uint64_t arr, int r) { return gld<float2>(arr + (b2 + r * rs2) * 8, vs2); };
         // stores take their own opaque copy of the stride: sharing the load addresses
         // would keep 16-32 scalar address pairs live across the whole tile
@@ -604,6 +664,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 apply_angles<NS, 1, false>(v, uf);
             } else {
                 cz2(rc);
+                cz_ready(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     float c, s;
@@ -634,6 +695,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     apply_angles<NS, 1, false>(v, uf);
                 } else {
                     if constexpr (!EARLY) cz1(rc);
+                    cz_ready(rc);
 #pragma unroll
                     for (int r = 0; r < kRegs; ++r) {
                         float c, s;
@@ -649,6 +711,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             } else {
                 double e = 0.0;
                 if constexpr (!EARLY) cz1(rc);
+                cz_ready(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     const float pz = fmaf(v[0][r].x, v[0][r].x, v[0][r].y * v[0][r].y);
@@ -668,6 +731,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             if constexpr (EARLY) cz1(rc);
             double gb = 0.0;
             mix_op<HIGH, FULL, 2, 2, 1, false, FB1>(lds, v, t, a.active, c1, gb);
+            cz_ready(rc);
             double e = 0.0;
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) {
@@ -708,6 +772,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             } else {
                 double gg = 0.0;
                 if constexpr (!EARLY) cz1(rc);
+                cz_ready(rc);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     const double cz = reg_cost(rc, cq, r);
@@ -743,7 +808,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
 // Layer constants of one pass for parameter set x, then one uniform dispatch on
 // the forms of the (up to two) mixer coefficients, so the butterfly code of each
 // path has no form branch.  Tiles g, g + a.G, ... below a.tiles.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool PART = false, bool WIDE = false>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART = false, bool WIDE = false, bool CT = false>
 __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g)
 {
     const double *x = a.params + (size_t)b * 2 * a.p;
@@ -772,15 +837,15 @@ __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double 
     constexpr bool TWO = KIND == FK_TURN || KIND == FK_LASTG || KIND == FK_BTURN;
     if constexpr (!FULL) {
         // general butterflies: one body serves both forms
-        pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
         return;
     }
     const int sel = (c1.formB ? 1 : 0) | (TWO && c2.formB ? 2 : 0);
-    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
-    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, false>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, false, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
     else if constexpr (TWO) {
-        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
-        else pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, true>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, true, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        else pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, true, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
     }
 }
 
