@@ -102,9 +102,14 @@ qq_status qq_device_count(int *count);
  *   device  HIP device ordinal
  * The handle canonicalises (eq. (4)-(5)), classifies the problem as integer
  * or real, and builds the cost diagonal C(z) of eq. (6) on the device once
- * (the "build once, bind many" reuse of the circuit-reuse section).
+ * (the "build once, bind many" reuse of the circuit-reuse section).  For
+ * n > 12 it also builds the per-tile cost tables that the complex64
+ * evaluation kernels read instead of the diagonal (C is quadratic, so a
+ * tile's 4096 values follow from its base bits): 576 bytes per 4096 states
+ * for each set layout, about 0.53 GB in all at n = 28 (2^28 states).
  * Errors: QQ_E_INVALID (n out of range, NULL H/out, non-finite entry),
- * QQ_E_TOO_LARGE (the diagonal does not fit the device), QQ_E_DEVICE, QQ_E_NOMEM.
+ * QQ_E_TOO_LARGE (the diagonal and its tables do not fit the device),
+ * QQ_E_DEVICE, QQ_E_NOMEM.
  */
 qq_status qq_problem_create(int n, const double *H, const double *f, double c0, int device, void *stream,
                             qq_problem **out);

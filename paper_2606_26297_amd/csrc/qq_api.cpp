@@ -579,26 +579,39 @@ double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128, bo
     return (double)pb->dim * (B * moves * es + (diag_reads + cross_reads) * d);
 }
 
-// Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
+// The tables a problem of n variables needs: one per set geometry of every pairing and per layout.
+std::vector<qq_problem::CostTab> cost_table_list(int n)
+{
+    std::vector<qq_problem::CostTab> tabs;
+    if (n <= kTileBits || n > kFastMaxN) return tabs;
+    auto add = [&](const SetDesc &sd, int lane_q) {
+        for (const auto &t : tabs)
+            if (t.high == sd.high && t.pos4 == sd.pos4 && t.pos8 == sd.pos8 && t.lane_q == lane_q) return;
+        tabs.push_back({sd.high, sd.pos4, sd.pos8, lane_q, 0});
+    };
+    for (int pr = 0; pr < (pairing_applies(n) ? kPairings : 1); ++pr)
+        for (const SetDesc &sd : make_sets(n, pr)) {
+            add(sd, sd.pos4);
+            add(sd, sd.pos8);
+        }
+    return tabs;
+}
+
+size_t cost_table_bytes(int n)
+{
+    if (n <= kTileBits || n > kFastMaxN) return 0;
+    return cost_table_list(n).size() * ((size_t)tiles_per_state(n) * kCostRow + 256 * 8) * sizeof(double);
+}
+
 // The per-tile cost tables of a problem (see qq_problem::CostTab): the rows on the device, the
 // per-thread constants (P(E) and l_Rj + sum_{q in E} b_q,Rj, with E the thread's lane and wave bits) on
 // the host from the canonical coefficients.
 qq_status build_cost_tables(qq_problem *pb, hipStream_t stream)
 {
     const int n = pb->n;
-    if (n <= kTileBits || n > kFastMaxN) return QQ_OK;
+    std::vector<qq_problem::CostTab> tabs = cost_table_list(n);
+    if (tabs.empty()) return QQ_OK;
     const uint64_t T = tiles_per_state(n);
-    std::vector<qq_problem::CostTab> tabs;
-    auto add = [&](const SetDesc &sd, int lane_q) {
-        for (const auto &t : tabs)
-            if (t.high == sd.high && t.pos4 == sd.pos4 && t.pos8 == sd.pos8 && t.lane_q == lane_q) return;
-        tabs.push_back({sd.high, sd.pos4, sd.pos8, lane_q, 0});
-    };
-    for (int pr = 0; pr < (pairing_applies(n) ? 3 : 1); ++pr)
-        for (const SetDesc &sd : make_sets(n, pr)) {
-            add(sd, sd.pos4);
-            add(sd, sd.pos8);
-        }
     const size_t per = (size_t)T * kCostRow + 256 * 8;
     if (hipMalloc((void **)&pb->d_ctab, per * tabs.size() * sizeof(double)) != hipSuccess)
         return fail(QQ_E_NOMEM, "hipMalloc(%zu) for the cost tables failed", per * tabs.size() * sizeof(double));
@@ -645,6 +658,7 @@ const double *find_cost_table(const qq_problem *pb, const SetDesc &sd, int lane_
     return nullptr;
 }
 
+// Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
 qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int B, int flags, char *ws,
                    const double *d_params, hipStream_t stream, bool capturing = false)
 {
@@ -1243,20 +1257,69 @@ double max_abs(const double *g, int m)
     return r;
 }
 
-// Recompute the flagged parameter sets of one problem with complex128 states (host in, host out).
-qq_status recompute_c128(qq_problem *pb, int p, const double *params, const std::vector<int> &sets, int flags,
-                         void *stream, double *energy, double *grad)
+// The flagged parameter sets of one problem, to be recomputed with complex128 states.
+struct C128Job {
+    qq_problem *pb;
+    int p;
+    const double *params;  // host [batch][2p]
+    std::vector<int> sets;
+    double *energy, *grad;  // host outputs, indexed by set
+};
+
+// Recompute every job's sets with complex128 states (host in, host out): the jobs share one workspace
+// (the largest any of them needs) and one device output buffer, run back to back on `stream` and are
+// read back with one synchronisation.  All problems are on one device.
+qq_status recompute_c128(std::vector<C128Job> &jobs, int flags, void *stream_)
 {
-    if (sets.empty()) return QQ_OK;
-    const int m = (int)sets.size(), w = 2 * p;
-    std::vector<double> x((size_t)m * w), e(m), g((size_t)m * w);
-    for (int i = 0; i < m; ++i) std::memcpy(&x[(size_t)i * w], params + (size_t)sets[i] * w, w * sizeof(double));
     const int f = (flags & (QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED)) | QQ_C128;
-    if (qq_status st = qq_evaluate(pb, p, m, x.data(), f, nullptr, 0, stream, e.data(), g.data()); st != QQ_OK)
+    const bool grad = flags & QQ_GRAD;
+    size_t wsmax = 0, nx = 0, nout = 0;
+    for (const C128Job &j : jobs) {
+        if (j.sets.empty()) continue;
+        const int m = (int)j.sets.size();
+        size_t w = 0;
+        if (qq_status st = qq_workspace_size(j.pb, j.p, m, f, &w); st != QQ_OK) return st;
+        wsmax = std::max(wsmax, w);
+        nx += (size_t)m * 2 * j.p;
+        nout += (size_t)m * (1 + (grad ? 2 * j.p : 0));
+    }
+    if (nx == 0) return QQ_OK;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const int device = jobs[0].pb->device;
+    QQ_HIP(hipSetDevice(device));
+    if (qq_status st = check_device_fits(device, wsmax + nout * sizeof(double), "the complex128 recomputation");
+        st != QQ_OK)
         return st;
-    for (int i = 0; i < m; ++i) {
-        energy[sets[i]] = e[i];
-        std::memcpy(grad + (size_t)sets[i] * w, &g[(size_t)i * w], w * sizeof(double));
+    DevBuf ws, out;
+    if (hipMalloc(&ws.p, wsmax) != hipSuccess || hipMalloc(&out.p, nout * sizeof(double)) != hipSuccess)
+        return fail(QQ_E_NOMEM, "hipMalloc of %zu + %zu bytes for the complex128 recomputation failed", wsmax,
+                    nout * sizeof(double));
+    double *d_out = static_cast<double *>(out.p);
+    std::vector<double> x(nx), h(nout);
+    size_t xo = 0, oo = 0;
+    for (const C128Job &j : jobs) {
+        if (j.sets.empty()) continue;
+        const int m = (int)j.sets.size(), w = 2 * j.p;
+        for (int i = 0; i < m; ++i)
+            std::memcpy(&x[xo + (size_t)i * w], j.params + (size_t)j.sets[i] * w, w * sizeof(double));
+        if (qq_status st = qq_evaluate(j.pb, j.p, m, &x[xo], f | QQ_OUT_ON_DEVICE, ws.p, wsmax, stream, d_out + oo,
+                                       grad ? d_out + oo + m : nullptr);
+            st != QQ_OK)
+            return st;
+        xo += (size_t)m * w;
+        oo += (size_t)m * (1 + (grad ? w : 0));
+    }
+    QQ_HIP(hipMemcpyAsync(h.data(), d_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    oo = 0;
+    for (C128Job &j : jobs) {
+        if (j.sets.empty()) continue;
+        const int m = (int)j.sets.size(), w = 2 * j.p;
+        for (int i = 0; i < m; ++i) {
+            j.energy[j.sets[i]] = h[oo + i];
+            if (grad) std::memcpy(j.grad + (size_t)j.sets[i] * w, &h[oo + m + (size_t)i * w], w * sizeof(double));
+        }
+        oo += (size_t)m * (1 + (grad ? w : 0));
     }
     return QQ_OK;
 }
@@ -1378,7 +1441,9 @@ qq_status qq_problem_create(int n, const double *H, const double *f, double c0, 
 
     pb->dim = 1ull << n;
     const size_t dbytes = (size_t)pb->dim * diag_bytes_of(pb->diag_type);
-    if (qq_status st = check_device_fits(device, dbytes, "the cost diagonal"); st != QQ_OK) return st;
+    if (qq_status st = check_device_fits(device, dbytes + cost_table_bytes(n), "the cost diagonal and its tables");
+        st != QQ_OK)
+        return st;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     QQ_HIP(hipSetDevice(device));
     const int np = (int)pb->pair_b.size();
@@ -2224,7 +2289,8 @@ static qq_status evaluate_guarded_impl(qq_problem *pb, int p, int batch, const d
     std::vector<double> err(batch);
     const std::vector<int> sets =
         guard_sets(pb, p, batch, grad ? g.data() : nullptr, tol, (flags & QQ_C128) != 0, up.data(), err.data());
-    if (qq_status st = recompute_c128(pb, p, params, sets, flags, stream, e.data(), g.data()); st != QQ_OK) return st;
+    std::vector<C128Job> jobs{{pb, p, params, sets, e.data(), g.data()}};
+    if (qq_status st = recompute_c128(jobs, flags, stream); st != QQ_OK) return st;
     if (grad)
         for (int b : sets) err[b] = kC128GradRel * max_abs(&g[(size_t)b * 2 * p], 2 * p);
     std::memcpy(energy_out, e.data(), batch * sizeof(double));
@@ -2263,17 +2329,19 @@ static qq_status evaluate_many_guarded_impl(int count, qq_problem *const *proble
         return st;
     std::vector<std::vector<int32_t>> up(count);
     std::vector<std::vector<double>> err(count);
+    std::vector<C128Job> jobs;
     for (int i = 0; i < count; ++i) {
         up[i].resize(batch[i]);
         err[i].resize(batch[i]);
-        const std::vector<int> sets =
+        std::vector<int> sets =
             guard_sets(problems[i], p[i], batch[i], grad ? g[i].data() : nullptr, tol, false, up[i].data(), err[i].data());
-        if (qq_status st = recompute_c128(problems[i], p[i], params[i], sets, flags, stream, e[i].data(), g[i].data());
-            st != QQ_OK)
-            return st;
-        if (grad)
-            for (int b : sets) err[i][b] = kC128GradRel * max_abs(&g[i][(size_t)b * 2 * p[i]], 2 * p[i]);
+        if (!sets.empty()) jobs.push_back({problems[i], p[i], params[i], std::move(sets), e[i].data(), g[i].data()});
     }
+    if (qq_status st = recompute_c128(jobs, flags, stream); st != QQ_OK) return st;
+    for (int i = 0; i < count; ++i)
+        if (grad)
+            for (int b = 0; b < batch[i]; ++b)
+                if (up[i][b]) err[i][b] = kC128GradRel * max_abs(&g[i][(size_t)b * 2 * p[i]], 2 * p[i]);
     for (int i = 0; i < count; ++i) {
         std::memcpy(energy_out[i], e[i].data(), batch[i] * sizeof(double));
         if (grad) std::memcpy(grad_out[i], g[i].data(), (size_t)batch[i] * 2 * p[i] * sizeof(double));
