@@ -192,11 +192,14 @@ struct qq_problem {
     };
     std::vector<CostTab> ctabs;
     double *d_ctab = nullptr;
+    // the same tables of the cross-QPU couplings alone (qq_set_allocation), read by the partitioned phases
+    std::vector<CostTab> xtabs;
+    double *d_xtab = nullptr;
 
     ~qq_problem()
     {
         void *ptrs[] = {d_diag, d_ell, d_ell_i, d_pair_ij, d_pair_b, d_pair_bi, d_regq, d_part_cq, d_qpu, d_tables, d_cross,
-                        d_part, d_ctab};
+                        d_part, d_ctab, d_xtab};
         if (dim) (void)hipSetDevice(device);
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
@@ -570,11 +573,11 @@ double pass_bytes(const qq_problem *pb, const PassPlan &pp, int B, bool c128, bo
             diag_reads += 1;
         if ((o.kind == OP_PHASE || (o.kind == OP_GGAMMA && (o.flags & OPF_UNPHASE))) && part) cross_reads += 1;
     }
-    // the specialised kernels read one cost-table row per tile of 4096 entries in place of the cost
-    // diagonal, and 5 of every 16 cross-diagonal entries, forming the rest from them
+    // the specialised kernels read one table row per tile of 4096 entries in place of the cost (and
+    // cross-QPU) diagonal, forming the 4096 values from it
     if (fast) {
         diag_reads *= kCostRow * sizeof(double) / (4096.0 * d);
-        cross_reads *= 5.0 / 16.0;
+        cross_reads *= kCostRow * sizeof(double) / (4096.0 * d);
     }
     return (double)pb->dim * (B * moves * es + (diag_reads + cross_reads) * d);
 }
@@ -603,40 +606,41 @@ size_t cost_table_bytes(int n)
     return cost_table_list(n).size() * ((size_t)tiles_per_state(n) * kCostRow + 256 * 8) * sizeof(double);
 }
 
-// The per-tile cost tables of a problem (see qq_problem::CostTab): the rows on the device, the
-// per-thread constants (P(E) and l_Rj + sum_{q in E} b_q,Rj, with E the thread's lane and wave bits) on
-// the host from the canonical coefficients.
-qq_status build_cost_tables(qq_problem *pb, hipStream_t stream)
+// Per-tile tables of one quadratic cost c0 + sum l_i z_i + sum_{i<j} b_ij z_i z_j (see
+// qq_problem::CostTab): the rows on the device from the device coefficient lists, the per-thread
+// constants (P(E) and l_Rj + sum_{q in E} b_q,Rj, with E the thread's lane and wave bits) on the host.
+// `ell` / `B` give the host coefficients; `*d_out` receives the one allocation.
+template <typename BF>
+qq_status build_tables(int n, const std::vector<double> &ell, BF B, const double *d_ell, int np,
+                       const int32_t *d_pij, const double *d_pb, double c0, std::vector<qq_problem::CostTab> &tabs,
+                       double **d_out, hipStream_t stream)
 {
-    const int n = pb->n;
-    std::vector<qq_problem::CostTab> tabs = cost_table_list(n);
+    tabs = cost_table_list(n);
     if (tabs.empty()) return QQ_OK;
     const uint64_t T = tiles_per_state(n);
     const size_t per = (size_t)T * kCostRow + 256 * 8;
-    if (hipMalloc((void **)&pb->d_ctab, per * tabs.size() * sizeof(double)) != hipSuccess)
+    if (hipMalloc((void **)d_out, per * tabs.size() * sizeof(double)) != hipSuccess)
         return fail(QQ_E_NOMEM, "hipMalloc(%zu) for the cost tables failed", per * tabs.size() * sizeof(double));
-    auto B = [&](int i, int j) { return i < j ? pb->b[(size_t)i * n + j] : pb->b[(size_t)j * n + i]; };
     std::vector<double> thr(256 * 8 * tabs.size(), 0.0);
-    const int np = (int)pb->pair_b.size();
     for (size_t k = 0; k < tabs.size(); ++k) {
         qq_problem::CostTab &tb = tabs[k];
         tb.off = k * per;
         const int lq = tb.lane_q, rq = lq == tb.pos4 ? tb.pos8 : tb.pos4;
-        QQ_HIP(launch_cost_table(n, tb.high, tb.pos4, tb.pos8, lq, rq, T, pb->d_ell, np, pb->d_pair_ij, pb->d_pair_b,
-                                 pb->c0, pb->d_ctab + tb.off, stream));
+        QQ_HIP(launch_cost_table(n, tb.high, tb.pos4, tb.pos8, lq, rq, T, d_ell, np, d_pij, d_pb, c0, *d_out + tb.off,
+                                 stream));
         const int eq[8] = {0, 1, 2, 3, lq, lq + 1, lq + 2, lq + 3};
         for (int t = 0; t < 256; ++t) {
             double P = 0.0;
             for (int a = 0; a < 8; ++a) {
                 if (!((t >> a) & 1)) continue;
-                P += pb->ell[eq[a]];
+                P += ell[eq[a]];
                 for (int c = a + 1; c < 8; ++c)
                     if ((t >> c) & 1) P += B(eq[a], eq[c]);
             }
             double *row = &thr[(k * 256 + t) * 8];
             row[0] = P;
             for (int j = 0; j < 4; ++j) {
-                double q = pb->ell[rq + j];
+                double q = ell[rq + j];
                 for (int a = 0; a < 8; ++a)
                     if ((t >> a) & 1) q += B(eq[a], rq + j);
                 row[1 + j] = q;
@@ -644,18 +648,32 @@ qq_status build_cost_tables(qq_problem *pb, hipStream_t stream)
         }
     }
     for (size_t k = 0; k < tabs.size(); ++k)
-        QQ_HIP(hipMemcpyAsync(pb->d_ctab + tabs[k].off + (size_t)T * kCostRow, &thr[k * 256 * 8], 256 * 8 * sizeof(double),
+        QQ_HIP(hipMemcpyAsync(*d_out + tabs[k].off + (size_t)T * kCostRow, &thr[k * 256 * 8], 256 * 8 * sizeof(double),
                               hipMemcpyHostToDevice, stream));
     QQ_HIP(hipStreamSynchronize(stream));
-    pb->ctabs = tabs;
     return QQ_OK;
+}
+
+// The cost tables of the whole cost (at problem creation).
+qq_status build_cost_tables(qq_problem *pb, hipStream_t stream)
+{
+    const int n = pb->n;
+    auto B = [&](int i, int j) { return i < j ? pb->b[(size_t)i * n + j] : pb->b[(size_t)j * n + i]; };
+    return build_tables(n, pb->ell, B, pb->d_ell, (int)pb->pair_b.size(), pb->d_pair_ij, pb->d_pair_b, pb->c0,
+                        pb->ctabs, &pb->d_ctab, stream);
+}
+
+const double *find_table(const std::vector<qq_problem::CostTab> &tabs, const double *base, const SetDesc &sd,
+                         int lane_q)
+{
+    for (const auto &t : tabs)
+        if (t.high == sd.high && t.pos4 == sd.pos4 && t.pos8 == sd.pos8 && t.lane_q == lane_q) return base + t.off;
+    return nullptr;
 }
 
 const double *find_cost_table(const qq_problem *pb, const SetDesc &sd, int lane_q)
 {
-    for (const auto &t : pb->ctabs)
-        if (t.high == sd.high && t.pos4 == sd.pos4 && t.pos8 == sd.pos8 && t.lane_q == lane_q) return pb->d_ctab + t.off;
-    return nullptr;
+    return find_table(pb->ctabs, pb->d_ctab, sd, lane_q);
 }
 
 // Run every pass of a plan and the final reduction.  `ws` is device memory laid out by `L`.
@@ -715,7 +733,6 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             fp.part = (flags & QQ_PARTITIONED) ? 1 : 0;
             fp.part_desc = pb->d_part;
             fp.part_tables = pb->d_tables;
-            fp.cross_diag = pb->d_cross;
             fp.B = B;
             fp.G = L.G;
             fp.p = p;
@@ -745,6 +762,12 @@ qq_status run_plan(qq_problem *pb, const Plan &plan, const Layout &L, int p, int
             fp.ctab = find_cost_table(pb, sd, pp.fkind == FK_FIRST ? sd.pos4 : sd.pos8);
             if (!fp.ctab) return fail(QQ_E_DEVICE, "no cost table for the set at qubits %d / %d", sd.pos4, sd.pos8);
             fp.cthr = fp.ctab + (size_t)T * kCostRow;
+            fp.xtab = fp.xthr = nullptr;
+            if (fp.part) {
+                fp.xtab = find_table(pb->xtabs, pb->d_xtab, sd, pp.fkind == FK_FIRST ? sd.pos4 : sd.pos8);
+                if (!fp.xtab) return fail(QQ_E_DEVICE, "no cross table for the set at qubits %d / %d", sd.pos4, sd.pos8);
+                fp.xthr = fp.xtab + (size_t)T * kCostRow;
+            }
             QQ_HIP(launch_fast_pass(pp.fkind, sd.high != 0, pb->diag_type, fp, stream));
         } else {
             QQ_HIP(launch_pass(a, c128, pp.nstates, pb->diag_type, stream));
@@ -1629,13 +1652,17 @@ qq_status qq_set_allocation(qq_problem *pb, int M, const int32_t *qpu_of_var, co
         total += 1ull << pd.nvars[m];
     }
     const int es = diag_bytes_of(pb->diag_type);
-    if (qq_status st = check_device_fits(pb->device, (size_t)pb->dim * es * 2, "the cross-QPU diagonal"); st != QQ_OK)
+    if (qq_status st = check_device_fits(pb->device, (size_t)pb->dim * es * 2 + 2 * cost_table_bytes(n),
+                                         "the cross-QPU diagonal and its tables");
+        st != QQ_OK)
         return st;
     QQ_HIP(hipSetDevice(pb->device));
     // release a previous allocation
-    void *olds[] = {pb->d_qpu, pb->d_tables, pb->d_cross, pb->d_part, pb->d_part_cq};
+    void *olds[] = {pb->d_qpu, pb->d_tables, pb->d_cross, pb->d_part, pb->d_part_cq, pb->d_xtab};
     for (void *q : olds)
         if (q) QQ_HIP(hipFree(q));
+    pb->d_xtab = nullptr;
+    pb->xtabs.clear();
     pb->d_part_cq = nullptr;
     pb->d_qpu = nullptr;
     pb->d_tables = pb->d_cross = nullptr;
@@ -1691,6 +1718,17 @@ qq_status qq_set_allocation(qq_problem *pb, int M, const int32_t *qpu_of_var, co
         QQ_HIP(launch_cost_diag(n, pb->diag_type, static_cast<double *>(zero_ell.p), static_cast<int32_t *>(zero_elli.p),
                                 nx, static_cast<int32_t *>(dij.p), static_cast<double *>(db.p),
                                 static_cast<int32_t *>(dbi.p), 0.0, 0, pb->d_cross, pb->dim, stream));
+        // and its per-tile tables (the partitioned phases of the complex64 kernels read these)
+        const std::vector<double> zeros(n, 0.0);
+        auto BX = [&](int i, int j) {
+            if (qpu_of_var[i] == qpu_of_var[j]) return 0.0;
+            return i < j ? pb->b[(size_t)i * n + j] : pb->b[(size_t)j * n + i];
+        };
+        if (qq_status st = build_tables(n, zeros, BX, static_cast<double *>(zero_ell.p), nx,
+                                        static_cast<int32_t *>(dij.p), static_cast<double *>(db.p), 0.0, pb->xtabs,
+                                        &pb->d_xtab, stream);
+            st != QQ_OK)
+            return st;
         QQ_HIP(hipDeviceSynchronize());
     }
     pb->num_qpus = M;

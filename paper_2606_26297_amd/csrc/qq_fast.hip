@@ -164,13 +164,14 @@ hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassPa
     a.blocked = pp.blocked;
     a.part = pp.part_desc;
     a.tables = pp.part_tables;
-    a.cross = pp.cross_diag;
     a.cq = pp.cq;
     a.pcq = pp.part_cq;
     a.pcq_runs = pp.part_cq_runs;
     a.shift = pp.shift;
     a.ctab = pp.ctab;
     a.cthr = pp.cthr;
+    a.xtab = pp.xtab;
+    a.xthr = pp.xthr;
     const bool part = pp.part != 0;
     switch (kind) {
     case FK_FIRST: return launch_kind<FK_FIRST>(a, high, diag_type, part, s);

@@ -138,7 +138,6 @@ struct FastPassParams {
     int part;  // 1: the phase is the product of the per-QPU local factors and the cross factor
     const PartDesc *part_desc;  // device
     const void *part_tables;
-    const void *cross_diag;
     int B, G, p, k;
     uint64_t tiles, dim_mask;
     int pos4, pos8, w1, w2, active, store_psi;
@@ -162,6 +161,9 @@ struct FastPassParams {
     // reads the cost
     const double *ctab;
     const double *cthr;
+    // the same for the cross-QPU couplings alone; required by the partitioned phases
+    const double *xtab;
+    const double *xthr;
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
 

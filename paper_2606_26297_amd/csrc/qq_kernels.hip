@@ -660,15 +660,18 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s)
 namespace {
 
 // One row per tile (layout with launch_cost_table's declaration): C(T) of the tile's base bits T
-// (c0, then l_i over T, then the couplings inside T) and G_q(T) = sum_{i in T} b_iq for the tile's
-// 12 qubits, combined into the per-lane, per-wave and per-register entries.
+// (c0, the l_i over T and the couplings inside T) and G_q(T) = sum_{i in T} b_iq for the tile's 12
+// qubits, combined into the per-lane, per-wave and per-register entries.  One wave per tile: lane k
+// takes the linear terms and couplings k, k + 64, ..., the wave sums them with butterflies, then
+// lane l writes entry l and lanes 0..7 the wave and register entries.
 __global__ void __launch_bounds__(256) cost_table_kernel(int n, int high, int pos4, int pos8, int lane_q, int reg_q,
                                                           uint64_t tiles, const double *ell, int npairs,
                                                           const int32_t *pij, const double *pb, double c0,
                                                           double *out)
 {
-    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tile >= tiles) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= tiles) return;  // whole waves
     const uint64_t T = high ? tile_base(tile, pos4, pos8, pos4 - 4, pos8 - pos4 - 4) : (tile << kTileBits);
     // slots 0..3: qubits 0..3, 4..7: lane_q .. lane_q + 3, 8..11: reg_q .. reg_q + 3
     auto slot = [&](int q) {
@@ -677,13 +680,13 @@ __global__ void __launch_bounds__(256) cost_table_kernel(int n, int high, int po
         if (q >= reg_q && q < reg_q + 4) return 8 + (q - reg_q);
         return -1;
     };
-    double C = c0;
-    for (int i = 0; i < n; ++i)
+    double C = 0.0;
+    for (int i = lane; i < n; i += 64)
         if ((T >> i) & 1ull) C += ell[i];
     double G[12];
 #pragma unroll
     for (int s = 0; s < 12; ++s) G[s] = 0.0;
-    for (int k = 0; k < npairs; ++k) {
+    for (int k = lane; k < npairs; k += 64) {
         const int i = pij[2 * k], j = pij[2 * k + 1];
         const double w = pb[k];
         const int si = slot(i), sj = slot(j);
@@ -699,20 +702,21 @@ __global__ void __launch_bounds__(256) cost_table_kernel(int n, int high, int po
                 if (u == s && on) G[u] += w;
         }
     }
-    double *row = out + tile * kCostRow;
-    for (int l = 0; l < 64; ++l) {
-        double z = C;
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
-            if ((l >> q) & 1) z += G[q];
-        row[l] = z;
+    for (int off = 32; off > 0; off >>= 1) {
+        C += __shfl_xor(C, off);
+#pragma unroll
+        for (int s = 0; s < 12; ++s) G[s] += __shfl_xor(G[s], off);
     }
-    row[64] = 0.0;
-    row[65] = G[6];
-    row[66] = G[7];
-    row[67] = G[6] + G[7];
+    C += c0;
+    double *row = out + tile * kCostRow;
+    double z = C;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) row[68 + j] = G[8 + j];
+    for (int q = 0; q < 6; ++q)
+        if ((lane >> q) & 1) z += G[q];
+    row[lane] = z;
+    if (lane < 4) row[64 + lane] = ((lane & 1) ? G[6] : 0.0) + ((lane & 2) ? G[7] : 0.0);
+    else if (lane < 8) row[64 + lane] = lane == 4 ? G[8] : lane == 5 ? G[9] : lane == 6 ? G[10] : G[11];
 }
 
 }  // namespace
@@ -721,7 +725,7 @@ hipError_t launch_cost_table(int n, int high, int pos4, int pos8, int lane_q, in
                              const double *d_ell, int npairs, const int32_t *d_pair_ij, const double *d_pair_b,
                              double c0, double *out, hipStream_t s)
 {
-    const unsigned grid = (unsigned)((tiles + 255) / 256);
+    const unsigned grid = (unsigned)((tiles + 3) / 4);
     hipLaunchKernelGGL(cost_table_kernel, dim3(grid), dim3(256), 0, s, n, high, pos4, pos8, lane_q, reg_q, tiles,
                        d_ell, npairs, d_pair_ij, d_pair_b, c0, out);
     return hipGetLastError();

@@ -241,13 +241,13 @@ __device__ __forceinline__ void run_chunk(const ManyInst &I, const ManyPass &P, 
     a.blocked = 0;
     a.part = nullptr;
     a.tables = nullptr;
-    a.cross = nullptr;
     a.cq = I.regq + 16 * (P.kind == FK_FIRST ? P.pos8 : P.pos4);
     a.pcq = nullptr;  // the persistent launch takes no partitioned phases
     a.pcq_runs = 0;
     a.shift = I.shift;
     a.ctab = P.ctab;
     a.cthr = P.cthr;
+    a.xtab = a.xthr = nullptr;  // no partitioned phases here
     double acc[3] = {0.0, 0.0, 0.0};
     const int g = (int)t0;
     switch (P.kind) {

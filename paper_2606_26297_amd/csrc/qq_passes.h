@@ -430,7 +430,6 @@ struct FastArgs {
     int blocked;           // 0: tiles g, g + G, ... ; 1: tiles [g T/G, (g + 1) T/G) (T a multiple of G)
     const PartDesc *part;  // partitioned phases (PART bodies only)
     const void *tables;    // packed per-QPU local tables
-    const void *cross;     // cross-QPU diagonal, 2^n entries
     const double *cq;      // 16 pair sums of the register qubits of the layout the diagonal is read in
     const double *pcq;     // partitioned: pair sums of every factor, [factor][run start][16]
     // Centre of the cost for the accumulations: the energy, the adjoint seed lambda = (C - shift) psi
@@ -445,12 +444,15 @@ struct FastArgs {
     // cthr[thread][8], the thread's own part (see reg_cost_form).
     const double *ctab;
     const double *cthr;
+    // the same for the cross-QPU couplings alone (partitioned phases)
+    const double *xtab;
+    const double *xthr;
 };
 
 // ---- partitioned phase (eq. (16)) --------------------------------------------------------------
 // The cost splits into per-QPU local parts C_m, each a function of that QPU's variables only (table
-// m is indexed by those bits in ascending variable order), and the cross part C_x (a diagonal over
-// all of z).  The phase is applied as the product of exp(-i gamma C_m), m = 0..M-1, and
+// m is indexed by those bits in ascending variable order), and the cross part C_x (a quadratic form
+// over all of z, formed from its per-tile table).  The phase is applied as the product of exp(-i gamma C_m), m = 0..M-1, and
 // exp(-i gamma C_x), each argument reduced on its own.  Table index of amplitude z for QPU m: the
 // bits of z on the QPU's variables, gathered in order.  The gather is additive over disjoint bit
 // sets, so for z = zb | e | (register bits) it is gather(zb) (per tile, scalar) + gather(e) (per
@@ -491,32 +493,34 @@ __device__ __forceinline__ uint32_t part_gather(uint64_t zb, uint64_t vmask)
 // uf[r] = the sum over the local factors and the cross factor of (gamma / 2 pi) C_m(z), each
 // term reduced on its own in FP64 to [-1/2, 1/2], the sum reduced again and rounded to float.
 // Layout: lanes hold qubits 0..3 (lane_lo) and qh, qh + 1 (lane_hi); registers hold qubits
-// qr..qr+3 (register stride rs); zb is the tile's wave-uniform first index; vd the lane's byte
-// offset into a DT diagonal.  Every factor is quadratic in z, so its 16 register values follow from
-// five reads (register 0 and the four single-bit registers) and the factor's pair sums among the
-// register qubits (a.pcq, laid out [factor][run start][16], the cross factor last), as for the
-// cost diagonal.  The angles do not depend on the state, so a pass can form them before it loads
-// any amplitude.
-template <typename DT, typename O>
+// qr..qr+3; zb is the tile's wave-uniform first index, `tile` its index in the pass's table.  Every
+// factor is quadratic in z, so its 16 register values follow from its value at register 0, its four
+// single-bit increments and its pair sums among the register qubits (a.pcq, laid out
+// [factor][run start][16], the cross factor last): five reads of a local table, or for the cross
+// factor its per-tile table (as reg_cost_form).  The angles do not depend on the state, so a pass
+// can form them before it loads any amplitude.
+template <typename DT>
 __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &a, double g2pi, uint64_t zb,
-                                            uint32_t lane_lo, uint32_t lane_hi, int qh, int qr, uint64_t rs, O vd)
+                                            uint32_t lane_lo, uint32_t lane_hi, int qh, int qr, uint64_t tile, int t)
 {
     // registers in two halves of 8, so the FP64 sums take 16 VGPRs, not 32
     constexpr int H = kRegs / 2;
     // opaque here, so the masks and lane tests derived from them are formed per tile instead of
     // hoisted out of the tile loop (where they would hold dozens of scalar registers throughout)
     asm volatile("" : "+s"(qh), "+s"(qr), "+v"(lane_lo), "+v"(lane_hi));
-    const uint64_t cross_a = (uint64_t)a.cross;
     const int M = a.part->nparts;
     const DT *tables = static_cast<const DT *>(a.tables);
     RegQ *pcq = (RegQ *)a.pcq;
-    // the five values of one factor -> its 8 register values of half h, reduced and added to u
-    auto add_factor = [&](const double (&e)[5], RegQ *w, int h, double (&u)[H], bool first) {
-        double k[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) k[j] = e[j + 1] - e[0];
+    // the cross factor's table row and per-thread constants
+    const double *xrow = a.xtab + tile * kCostRow;
+    const double *xth = a.xthr + 8 * t;
+    cdouble_t *xu = (cdouble_t *)xrow;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(t >> 6);
+    // one factor's value at register 0 of half h (v0) and its four register increments k -> its 8
+    // register values of half h, reduced and added to u
+    auto add_factor = [&](double v0, const double (&k)[4], RegQ *w, int h, double (&u)[H], bool first) {
         double v[H];
-        v[0] = h ? e[4] : e[0];
+        v[0] = v0;
 #pragma unroll
         for (int i = 1; i < H; ++i) {
             const int j = __builtin_ctz(i);
@@ -532,11 +536,11 @@ __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &
     for (int h = 0; h < 2; ++h) {
         double u[H];
         {
-            double e[5];
-            e[0] = (double)gld<DT>(cross_a + zb * sizeof(DT), vd);
+            double k[4];
+            const double z0 = (xrow[t & 63] + xu[64 + wave]) + xth[0];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) e[j + 1] = (double)gld<DT>(cross_a + (zb + (rs << j)) * sizeof(DT), vd);
-            add_factor(e, pcq + ((size_t)M * a.pcq_runs + qr) * kRegs, h, u, true);
+            for (int j = 0; j < 4; ++j) k[j] = xu[68 + j] + xth[1 + j];
+            add_factor(h ? z0 + k[3] : z0, k, pcq + ((size_t)M * a.pcq_runs + qr) * kRegs, h, u, true);
         }
         for (int m = 0; m < M; ++m) {
             const uint64_t vm = a.part->vmask[m];
@@ -551,7 +555,10 @@ __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 e[j + 1] = (double)gld<DT>(tab, (L + part_contrib(vm, qr + j)) * (uint32_t)sizeof(DT));
-            add_factor(e, pcq + ((size_t)m * a.pcq_runs + qr) * kRegs, h, u, false);
+            double k[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) k[j] = e[j + 1] - e[0];
+            add_factor(h ? e[4] : e[0], k, pcq + ((size_t)m * a.pcq_runs + qr) * kRegs, h, u, false);
         }
 #pragma unroll
         for (int i = 0; i < H; ++i) uf[h * H + i] = (float)(u[i] - rint(u[i]));
@@ -658,7 +665,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         if constexpr (KIND == FK_FIRST) {
             if constexpr (PART) {
                 float uf[kRegs];
-                part_angles<DT>(uf, a, g2pi, b2, lane_lo, lane_hi, a.pos4, a.pos8, rs2, vd2);
+                part_angles<DT>(uf, a, g2pi, b2, lane_lo, lane_hi, a.pos4, a.pos8, tile, t);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) v[0][r] = make_float2((float)a.amp0, 0.0f);
                 apply_angles<NS, 1, false>(v, uf);
@@ -691,7 +698,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             } else if constexpr (KIND == FK_TURN) {
                 if constexpr (PART) {
                     float uf[kRegs];
-                    part_angles<DT>(uf, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, rs1, vd1);
+                    part_angles<DT>(uf, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, tile, t);
                     apply_angles<NS, 1, false>(v, uf);
                 } else {
                     if constexpr (!EARLY) cz1(rc);
@@ -752,7 +759,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             // partitioned adjoint turn: the un-phase angles (layout 1) before any amplitude is live
             float uf_b[kRegs];
             if constexpr (KIND == FK_BTURN && PART)
-                part_angles<DT>(uf_b, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, rs1, vd1);
+                part_angles<DT>(uf_b, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, tile, t);
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) {
                 v[0][r] = ld2(psi_a, r);
