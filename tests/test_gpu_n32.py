@@ -16,6 +16,12 @@ any size (1e-5 relative; energy |dE| / max(|E|, sigma_C), gradient
     diagonal against the oracle's one-index sums (bit for bit).
 Device memory: the diagonal and the cross diagonal (FP64, 32 GiB each) plus the
 states of the evaluation; at most about 160 GiB at once.
+
+At the maximum size, n = 34 (QQ_MAX_N): an integer cluster-product instance (couplings only inside
+blocks, some of which straddle the 4-qubit runs of every set, so the per-tile cost tables carry
+couplings between tile and base bits) whose energy is c0 plus the sum of the per-block oracle
+energies; energy only (one complex64 state of 128 GiB, a 2-byte diagonal of 32 GiB, 18 GiB of
+cost tables).
 """
 import numpy as np
 import pytest
@@ -220,5 +226,35 @@ def test_n32_dense_gradient_vs_central_differences():
         print(f"fd {fd} adjoint {g_mono[0]}", flush=True)
         assert g_rel(g_mono, fd) <= 1e-5, (g_mono, fd)
         assert g_rel(g_part, fd) <= 1e-5, (g_part, fd)
+    finally:
+        pb.close()
+
+
+def test_n34_cluster_product_energy_at_the_maximum_size():
+    import torch
+
+    torch.cuda.empty_cache()
+    n = N.QQ_MAX_N
+    sizes = [7, 7, 7, 7, 6]
+    rng = np.random.default_rng(81)
+    H = np.zeros((n, n))
+    blocks, off = [], 0
+    for m in sizes:
+        H[off:off + m, off:off + m] = np.triu(rng.integers(-3, 4, size=(m, m))).astype(float)
+        blocks.append((off, m))
+        off += m
+    c0 = 2.0
+    pb = Problem(H, None, c0)
+    try:
+        assert pb.info.is_integer and pb.info.diag_bytes == 2
+        p, B = 2, 1
+        x = W.random_params(p, B, 82)
+        print(f"n = {n}: energy-only evaluation, p = {p}", flush=True)
+        e = pb.evaluate(x)
+        eref = c0
+        for o, m in blocks:
+            d = O.cost_diagonal(H[o:o + m, o:o + m], None, 0.0)
+            eref += O.gradient(d, x[0])[0]
+        assert e_rel(e[0], eref, pb.info.sigma_c) <= 1e-5, (e[0], eref)
     finally:
         pb.close()

@@ -5,7 +5,9 @@
 * the set pairing and the set order change which qubits share a pass and where
   the phase is applied between two mixers, hence the complex64 rounding: every
   (pairing, set order) is checked against the closed form of a separable n = 28
-  problem (1e-5 relative);
+  problem (1e-5 relative) and, on a coupled n = 28 instance (which exercises every
+  pairing's per-tile cost tables), against the complex128 path, which reads the
+  cost diagonal (energy 1e-5 relative, gradient within the stated complex64 bound);
 * the autotuner pins a schedule that then evaluates correctly (oracle, 1e-5),
   writes its JSON-lines cache and reads it back without timing.
 """
@@ -79,6 +81,25 @@ def test_every_set_pairing_and_order_matches_the_separable_closed_form_at_n28():
                               {"workgroups_per_state": 256, "set_pairing": pairing, "set_order": set_order})
             e = pb.evaluate(x)
             assert np.max(np.abs(e - eref) / np.maximum(np.abs(eref), sig)) <= 1e-5, (pairing, set_order)
+
+
+def test_every_set_pairing_and_order_on_a_coupled_n28_instance_vs_complex128():
+    n, p, B = 28, 2, 2
+    inst = W.dense_gaussian_upper(n, 56)  # every pair coupled: every table entry sums many terms
+    pb = Problem(inst.H, inst.f, inst.c0)
+    x = W.random_params(p, B, 57)
+    sig = pb.info.sigma_c
+    e128, g128 = pb.evaluate(x, grad=True, c128=True)
+    for pairing in (0, 1, 2):
+        for set_order in (0, 1):
+            N.qq_set_schedule(pb.handle, p, B, GRAD,
+                              {"workgroups_per_state": 256, "set_pairing": pairing, "set_order": set_order})
+            e, g = pb.evaluate(x, grad=True)
+            assert np.max(np.abs(e - e128) / np.maximum(np.abs(e128), sig)) <= 1e-5, (pairing, set_order)
+            for b in range(B):
+                gmax = np.max(np.abs(g128[b]))
+                bound = N.QQ_GUARD_REL * gmax + N.QQ_GUARD_K * 2.0 ** -24 * sig ** 2 * 2.0 ** (-n / 2)
+                assert np.max(np.abs(g[b] - g128[b])) <= bound, (pairing, set_order, b)
 
 
 def test_invalid_schedules_are_rejected():
