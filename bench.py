@@ -737,6 +737,8 @@ def main():
                     help="with --uneven-only: time only the persistent launch (no per-problem launches)")
     ap.add_argument("--aux-only", action="store_true",
                     help="run only the cost-diagonal / probabilities / top-k leg on the timed instance")
+    ap.add_argument("--no-host-buffers", action="store_true",
+                    help="skip the step with host parameters and outputs")
     ap.add_argument("--many-options", default=None, metavar="TILES_PER_CHUNK:MAX_WORKGROUPS",
                     help="pin the persistent-launch options of the uneven batch instead of autotuning them")
     ap.add_argument("--summarize-counters", nargs=5, default=None,
@@ -877,6 +879,25 @@ def main():
            "hbm_GBps_step": round(step_bytes / (ms_per_step / 1000.0) / 1e9, 1),
            "algorithmic_bytes_per_eval": step_bytes / S,
            "roofline": roofline, "kernels": kernels}
+
+    if not args.no_host_buffers:
+        # the same step with the parameters read from and the results written to pageable host memory
+        # (the PCIe-inclusive rate; the C ABI's default when no *_ON_DEVICE flag is given)
+        progress("one step with host parameters and outputs")
+        hflags = N.QQ_ENERGY | N.QQ_GRAD
+        xh = np.ascontiguousarray(x)
+        eh, gh = np.empty(S), np.empty((S, 2 * p))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for w in range(S // B):
+            N.qq_evaluate(pb.handle, p, B, xh[w * B:(w + 1) * B], hflags, ws, ws_bytes, stream, eh[w * B:(w + 1) * B],
+                          gh[w * B:(w + 1) * B])
+        th = time.perf_counter() - t0
+        out["host_buffers"] = {"evals_per_s": round(S / th, 3), "ms_per_step": round(1000.0 * th, 3),
+                               "equal_to_device_path": bool(np.array_equal(eh, e_out.cpu().numpy()) and
+                                                            np.array_equal(gh, g_out.cpu().numpy())),
+                               "note": "one step; parameters copied in and results copied out over PCIe per "
+                                       "wave, each call synchronising"}
 
     # the other legs allocate their own memory: release the timed workspace first
     del ws
