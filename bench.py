@@ -190,6 +190,50 @@ def cpu_baseline():
             }}
 
 
+def oracle_multicore_uneven(max_workers=15, every=4):
+    """The oracle on every `every`-th problem of the uneven batch (energy + adjoint gradient with the cost
+    diagonal), spread over independent forked processes, one per core (each pinned to its own core, the
+    problems split by the work estimate n 2^n p, largest first): the oracle's throughput on C cores.
+    Runs before this process touches the GPU, so the children hold no device state."""
+    import multiprocessing as mp
+
+    from oracle import oracle as O
+    from paper_2606_26297_amd import workloads as W
+
+    cores = sorted(os.sched_getaffinity(0))[:max_workers]
+    items = W.workload4()
+    sel = list(range(0, len(items), every))
+    work = {k: items[k][0].n * (1 << items[k][0].n) * (items[k][1].shape[1] // 2) for k in range(len(items))}
+    parts = [[] for _ in cores]
+    loads = [0.0] * len(cores)
+    for k in sorted(sel, key=lambda k: -work[k]):
+        j = loads.index(min(loads))
+        parts[j].append(k)
+        loads[j] += work[k]
+
+    def run(core, ks):
+        os.sched_setaffinity(0, {core})
+        for k in ks:
+            inst, x = items[k]
+            O.gradient(O.cost_diagonal(inst.H, inst.f, inst.c0), x[0])
+
+    ctx = mp.get_context("fork")
+    procs = [ctx.Process(target=run, args=(c, ks)) for c, ks in zip(cores, parts) if ks]
+    t0 = time.perf_counter()
+    for pr in procs:
+        pr.start()
+    for pr in procs:
+        pr.join()
+    wall = time.perf_counter() - t0
+    ok = all(pr.exitcode == 0 for pr in procs)
+    scale = sum(work.values()) / sum(work[k] for k in sel)
+    return {"cores": len(procs), "problems_sample": len(sel), "seconds_sample": round(wall, 2),
+            "extrapolated_seconds_for_512": round(wall * scale, 1), "problems_per_s": round(len(sel) / wall, 3),
+            "all_workers_ok": ok,
+            "sample": f"every {every}th problem ({len(sel)}), one forked process per core, each pinned, the "
+                      "problems split by the work estimate n 2^n p; scaled to 512 by the work sum"}
+
+
 def progress(msg):
     """Stage lines on stderr (stdout carries only the JSON line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -772,6 +816,11 @@ def main():
     from paper_2606_26297_amd import workloads as W
     from paper_2606_26297_amd.qaoa import Problem
 
+    oracle_cores = None
+    if not (args.no_cpu_baseline or args.uneven_only or args.aux_only):
+        progress("oracle on several cores (before the GPU is touched)")
+        oracle_cores = oracle_multicore_uneven()
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     pinned_many = None
@@ -983,6 +1032,8 @@ def main():
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()
+        if oracle_cores is not None:
+            out["cpu_baseline"]["configs"]["workload4_uneven512"]["multi_core"] = oracle_cores
     print(json.dumps(out), flush=True)
 
 
