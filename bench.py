@@ -758,7 +758,7 @@ def summarize_counters(workload, stats_dir, fetch_dir, write_dir, command, only=
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--wave", type=int, default=64, help="starts per qq_evaluate call")
     ap.add_argument("--starts", type=int, default=64)
@@ -877,14 +877,14 @@ def main():
     progress(f"timing {args.steps} steps")
     N.qq_profile_enable(True)
     N.qq_profile_read()  # clear
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps (recorded on the launch stream, read after the timed region)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         step()
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     N.qq_profile_enable(False)
@@ -892,6 +892,7 @@ def main():
     wall = t1 - t0
     ms_per_step = 1000.0 * wall / args.steps
     value = S * args.steps / wall
+    step_ms = [round(evs[i].elapsed_time(evs[i + 1]), 3) for i in range(args.steps)]
 
     # roofline of the dominant kernel (the instantiation with the largest total time)
     by_kind = {}
@@ -925,6 +926,7 @@ def main():
            "config": {"workload": f"regular3_n{args.n}_p{p}_starts{S}", "n": args.n, "p": p, "starts": S,
                       "wave": B, "state": "complex64", "accumulators": "fp64"},
            "schedule": schedule,
+           "step_ms_each": step_ms, "step_ms_median": round(float(np.median(step_ms)), 3),
            "hbm_GBps_step": round(step_bytes / (ms_per_step / 1000.0) / 1e9, 1),
            "algorithmic_bytes_per_eval": step_bytes / S,
            "roofline": roofline, "kernels": kernels}
