@@ -462,6 +462,8 @@ def aux_kernels(dev, inst, x):
     from paper_2606_26297_amd import native as N
     from paper_2606_26297_amd.qaoa import Problem
 
+    # one creation first, so the timed one does not include the first touch of fresh device pages
+    Problem(inst.H, inst.f, inst.c0, device=0).close()
     N.qq_profile_enable(True)
     N.qq_profile_read()
     pb = Problem(inst.H, inst.f, inst.c0, device=0)
@@ -594,6 +596,7 @@ def multi_qpu(dev):
 
     inst, x, alloc = W.workload5()
     n, p, B = inst.H.shape[0], x.shape[1] // 2, x.shape[0]
+    Problem(inst.H, inst.f, inst.c0, device=0).close()  # first touch of the 32 GiB outside the timing
     N.qq_profile_enable(True)
     N.qq_profile_read()
     pb = Problem(inst.H, inst.f, inst.c0, device=0)

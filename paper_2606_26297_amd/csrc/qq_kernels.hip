@@ -287,60 +287,108 @@ __global__ void __launch_bounds__(256) finalize_kernel(const FinalizeArgs a)
 }
 
 // ---- cost diagonal (eq. (6)) ---------------------------------------------------------------
-constexpr int kMaxPairs = QQ_MAX_N * (QQ_MAX_N - 1) / 2;
+// Four basis indices per thread.  Real problems: FP64 sum in the canonical order (c0, then l_i for
+// ascending i, then b_ij row-major) over the set bits of z; integer problems: exact int32 sum of the
+// same terms.
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+    T v[4];
+};
 
-// One thread per basis index z.  Real problems: FP64 sum in the canonical order
-// (c0, then l_i for ascending i, then b_ij row-major) over the set bits of z;
-// integer problems: exact int32 sum of the same terms.
-template <bool INT, typename DT, typename Z>
+template <bool INT, typename DT>
 __global__ void __launch_bounds__(256) cost_diag_kernel(int n, uint64_t dim, const double *ell, const int32_t *ell_i,
                                                          int npairs, const int32_t *pij, const double *pb,
                                                          const int32_t *pbi, double c0, int32_t c0_i, DT *out)
 {
-    // Every coefficient index is wave-uniform, so the coefficients come through the scalar cache; each
-    // thread carries kPer indices through the same coefficient loop (one coefficient load serves them
-    // all).  The additions for one index are taken in the canonical order (c0, l_i ascending, b_ij
-    // row-major), adding a term only where its bits are set, so the FP64 entries equal the one-index
-    // sums bit for bit.  Z: 32-bit indices while 2^n fits, 64-bit beyond.
-    constexpr int kPer = 4;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t z0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z0 < dim; z0 += stride * kPer) {
-        Z z[kPer];
-        typename std::conditional<INT, int32_t, double>::type acc[kPer];
+    // A wave takes 256 consecutive indices z = zb + 4 l + u (lane l, u = 0..3): bits 0..7 vary inside the
+    // wave, bits 8 and up are those of zb, the same for the whole wave.  A coupling row i >= 8 whose
+    // bit is clear in zb is skipped by the whole wave; a term whose other bits are all >= 8 adds its
+    // coefficient or the neutral element chosen once for the wave (-0.0 in FP64: x + (-0.0) == x for
+    // every x, so an absent term leaves the sum's bits unchanged); a term with bits below 8 is added
+    // where the index's bits are set.  The coefficients are wave-uniform (scalar cache).  Each index
+    // adds its present terms in the canonical order, so the FP64 entries equal the one-index sums bit
+    // for bit.  The pairs are in row-major order with i < j (the canonical form's order).
+    using Acc = typename std::conditional<INT, int32_t, double>::type;
+    constexpr int kLow = 8;
+    const Acc neutral = INT ? (Acc)0 : (Acc)-0.0;
+    // first pair of every row (s_rows[n] = npairs), from the row-major pair list
+    __shared__ int s_rows[QQ_MAX_N + 1];
+    if ((int)threadIdx.x <= n) s_rows[threadIdx.x] = npairs;
+    __syncthreads();
+    for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
+        const int r = pij[2 * k];
+        if (k == 0 || pij[2 * k - 2] != r) s_rows[r] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int r = n - 1; r >= 0; --r) s_rows[r] = min(s_rows[r], s_rows[r + 1]);
+    __syncthreads();
+    // lane r holds the first pair of row r; read with readlane (no memory latency in the row loop)
+    const int vrows = s_rows[min((int)(threadIdx.x & 63), n)];
+
+    const uint32_t lo = 4u * (uint32_t)(threadIdx.x & 63);
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t w = uni64((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); (w << kLow) < dim;
+         w += nw) {
+        const uint64_t zb = w << kLow;
+        Acc acc[4];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            z[u] = (Z)(z0 + u * stride);
-            if constexpr (INT) acc[u] = c0_i;
-            else acc[u] = c0;
-        }
+        for (int u = 0; u < 4; ++u) acc[u] = INT ? (Acc)c0_i : (Acc)c0;
         for (int i = 0; i < n; ++i) {
             const int iu = __builtin_amdgcn_readfirstlane(i);
-            if constexpr (INT) {
-                const int32_t l = ell_i[iu];
+            const Acc l = INT ? (Acc)ell_i[iu] : (Acc)ell[iu];
+            if (iu < kLow) {
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) acc[u] += ((z[u] >> iu) & 1) ? l : 0;
+                for (int u = 0; u < 4; ++u) acc[u] = (((lo + u) >> iu) & 1u) ? acc[u] + l : acc[u];
             } else {
-                const double l = ell[iu];
+                const Acc lu = ((zb >> iu) & 1ull) ? l : neutral;
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) acc[u] = ((z[u] >> iu) & 1) ? acc[u] + l : acc[u];
+                for (int u = 0; u < 4; ++u) acc[u] += lu;
             }
         }
-        for (int k = 0; k < npairs; ++k) {
-            const int ku = __builtin_amdgcn_readfirstlane(k);
-            const int a = pij[2 * ku], b = pij[2 * ku + 1];
-            if constexpr (INT) {
-                const int32_t w = pbi[ku];
+        for (int r = 0; r < n; ++r) {
+            const int ru = __builtin_amdgcn_readfirstlane(r);
+            if (ru >= kLow && !((zb >> ru) & 1ull)) continue;  // the row is absent for the whole wave
+            const int k0 = __builtin_amdgcn_readlane(vrows, ru);
+            const int k1 = __builtin_amdgcn_readlane(vrows, ru + 1);
+            if (ru >= kLow) {
+                // both bits are wave-uniform: the coefficient or the neutral element, added everywhere
+
+                for (int k = k0; k < k1; ++k) {
+                    const int ku = __builtin_amdgcn_readfirstlane(k);
+                    const int j = pij[2 * ku + 1];
+                    const Acc wv = INT ? (Acc)pbi[ku] : (Acc)pb[ku];
+                    const Acc wu = ((zb >> j) & 1ull) ? wv : neutral;
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) acc[u] += ((z[u] >> a) & (z[u] >> b) & 1) ? w : 0;
+                    for (int u = 0; u < 4; ++u) acc[u] += wu;
+                }
             } else {
-                const double w = pb[ku];
+                // bit r varies inside the wave; bit j does below 8, is wave-uniform from 8 on
+
+                for (int k = k0; k < k1; ++k) {
+                    const int ku = __builtin_amdgcn_readfirstlane(k);
+                    const int j = pij[2 * ku + 1];
+                    const Acc wv = INT ? (Acc)pbi[ku] : (Acc)pb[ku];
+                    const uint32_t hj = (uint32_t)((zb >> j) & 1ull);
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) acc[u] = ((z[u] >> a) & (z[u] >> b) & 1) ? acc[u] + w : acc[u];
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t bj = j < kLow ? ((lo + u) >> j) & 1u : hj;
+                        acc[u] = (((lo + u) >> ru) & bj & 1u) ? acc[u] + wv : acc[u];
+                    }
+                }
             }
         }
+        const uint64_t z = zb + lo;
+        if (z + 4 <= dim) {
+            Quad<DT> q;
 #pragma unroll
-        for (int u = 0; u < kPer; ++u)
-            if (z0 + u * stride < dim) out[z0 + u * stride] = (DT)acc[u];
+            for (int u = 0; u < 4; ++u) q.v[u] = (DT)acc[u];
+            *reinterpret_cast<Quad<DT> *>(out + z) = q;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (z + u < dim) out[z + u] = (DT)acc[u];
+        }
     }
 }
 
@@ -735,24 +783,15 @@ hipError_t launch_cost_diag(int n, int diag_type, const double *d_ell, const int
                             const int32_t *d_pair_ij, const double *d_pair_b, const int32_t *d_pair_bi, double c0,
                             int32_t c0_i, void *d_out, uint64_t dim, hipStream_t s)
 {
+    // 256 indices per wave, 1024 per workgroup of four waves
     const dim3 grid(grid_for((dim + 3) / 4, 65536)), block(256);
-    const bool z32 = dim <= (1ull << 32);
-#define QQ_COST_DIAG(INT, DT, Z)                                                                                  \
-    hipLaunchKernelGGL((cost_diag_kernel<INT, DT, Z>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs, d_pair_ij, \
+#define QQ_COST_DIAG(INT, DT)                                                                                     \
+    hipLaunchKernelGGL((cost_diag_kernel<INT, DT>), grid, block, 0, s, n, dim, d_ell, d_ell_i, npairs, d_pair_ij,   \
                        d_pair_b, d_pair_bi, c0, c0_i, static_cast<DT *>(d_out))
     switch (diag_type) {
-    case DIAG_F64:
-        if (z32) QQ_COST_DIAG(false, double, uint32_t);
-        else QQ_COST_DIAG(false, double, uint64_t);
-        break;
-    case DIAG_I32:
-        if (z32) QQ_COST_DIAG(true, int32_t, uint32_t);
-        else QQ_COST_DIAG(true, int32_t, uint64_t);
-        break;
-    default:
-        if (z32) QQ_COST_DIAG(true, int16_t, uint32_t);
-        else QQ_COST_DIAG(true, int16_t, uint64_t);
-        break;
+    case DIAG_F64: QQ_COST_DIAG(false, double); break;
+    case DIAG_I32: QQ_COST_DIAG(true, int32_t); break;
+    default: QQ_COST_DIAG(true, int16_t); break;
     }
 #undef QQ_COST_DIAG
     return hipGetLastError();
