@@ -125,8 +125,10 @@ template <int KIND>
 hipError_t launch_kind(const FastArgs &a, bool high, int diag_type, bool part, hipStream_t s)
 {
     if (!high) return launch_k<KIND, false, true>(a, diag_type, part, s);  // the low set is always qubits 0..11
-    // largest layout-1 lane offset: (15 + 3 * 2^pos8) amplitudes of 8 bytes
-    const bool wide = ((15ull + (3ull << a.pos8)) * 8ull) >> 32 != 0;
+    // largest layout-1 lane offset: (15 + 3 * 2^q) amplitudes of 8 bytes, q = pos8 or its address
+    // position with interleaved psi / lambda blocks
+    const int q8 = a.pos8 + (a.ilv && a.pos8 >= a.ilv);
+    const bool wide = ((15ull + (3ull << q8)) * 8ull) >> 32 != 0;
     if (a.active == 0x0ff0) {
         if (wide) return hipErrorInvalidValue;  // full high sets stay below qubit 28 for n <= 34
         return launch_k<KIND, true, true>(a, diag_type, part, s);
@@ -172,6 +174,7 @@ hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassPa
     a.cthr = pp.cthr;
     a.xtab = pp.xtab;
     a.xthr = pp.xthr;
+    a.ilv = pp.ilv;
     const bool part = pp.part != 0;
     switch (kind) {
     case FK_FIRST: return launch_kind<FK_FIRST>(a, high, diag_type, part, s);

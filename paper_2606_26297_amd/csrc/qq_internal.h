@@ -164,6 +164,7 @@ struct FastPassParams {
     // the same for the cross-QPU couplings alone; required by the partitioned phases
     const double *xtab;
     const double *xthr;
+    int ilv;  // 0, or K: psi and lambda in alternating blocks of 2^K amplitudes (see Layout::ilv)
 };
 hipError_t launch_fast_pass(int kind, bool high, int diag_type, const FastPassParams &pp, hipStream_t s);
 

@@ -248,6 +248,7 @@ __device__ __forceinline__ void run_chunk(const ManyInst &I, const ManyPass &P, 
     a.ctab = P.ctab;
     a.cthr = P.cthr;
     a.xtab = a.xthr = nullptr;  // no partitioned phases here
+    a.ilv = 0;                  // separate psi and lambda arrays
     double acc[3] = {0.0, 0.0, 0.0};
     const int g = (int)t0;
     switch (P.kind) {

@@ -122,6 +122,7 @@ __device__ __forceinline__ double reg_cost(RegCost &c, RegQ *cq, int r)
 // G_Rj(T); the thread's P(E) and l_Rj + sum_{q in E} b_q,Rj are per-thread constants (thr, 8 doubles).
 // Exact for integer costs; for real ones within a few units in the last place of the diagonal's
 // canonical sums.
+
 // The values one tile's formation reads: the lane's and the wave's entries and the four register
 // increments of the row (wave-uniform, read through the constant address space so they take scalar
 // loads), the thread's five constants.
@@ -447,16 +448,20 @@ struct FastArgs {
     // the same for the cross-QPU couplings alone (partitioned phases)
     const double *xtab;
     const double *xthr;
+    // 0: psi and lambda are separate arrays; K > 0: their blocks of 2^K amplitudes alternate (lambda's
+    // block right after psi's), so index bit q >= K of a state sits at address bit q + 1
+    int ilv;
 };
 
 // ---- partitioned phase (eq. (16)) --------------------------------------------------------------
 // The cost splits into per-QPU local parts C_m, each a function of that QPU's variables only (table
 // m is indexed by those bits in ascending variable order), and the cross part C_x (a quadratic form
-// over all of z, formed from its per-tile table).  The phase is applied as the product of exp(-i gamma C_m), m = 0..M-1, and
-// exp(-i gamma C_x), each argument reduced on its own.  Table index of amplitude z for QPU m: the
-// bits of z on the QPU's variables, gathered in order.  The gather is additive over disjoint bit
-// sets, so for z = zb | e | (register bits) it is gather(zb) (per tile, scalar) + gather(e) (per
-// lane) + the register bits' contributions (scalar, one per register bit).
+// over all of z, formed from its per-tile table).  The phase is applied as the product of
+// exp(-i gamma C_m), m = 0..M-1, and exp(-i gamma C_x), each argument reduced on its own.  Table
+// index of amplitude z for QPU m: the bits of z on the QPU's variables, gathered in order.  The
+// gather is additive over disjoint bit sets, so for z = zb | e | (register bits) it is gather(zb)
+// (per tile, scalar) + gather(e) (per lane) + the register bits' contributions (scalar, one per
+// register bit).
 
 // 2^(rank of qubit q among the QPU's variables) if q is on the QPU, else 0.
 __device__ __forceinline__ uint32_t part_contrib(uint64_t vmask, int q)
@@ -607,11 +612,17 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
     const uint32_t lane_lo = t & 15, lane_hi = (t >> 4) & 3;
     // WIDE: the layout-1 lane offsets (lane bits on qubits pos8, pos8 + 1) need 64 bits
     using O1 = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+    // index offsets (the cost diagonal, the partitioned gathers) and state address offsets: with
+    // interleaved psi / lambda blocks (a.ilv = K) a run of four qubits at q >= K sits at q + 1 (no run
+    // straddles K); partitioned evaluations keep separate arrays
+    const int K = PART ? 0 : a.ilv;
+    const int s4 = a.pos4 + (K && a.pos4 >= K), s8 = a.pos8 + (K && a.pos8 >= K);
     const uint32_t e2 = lane_lo + (lane_hi << a.pos4);
     const O1 e1 = (O1)lane_lo + ((O1)lane_hi << a.pos8);
-    const uint32_t vs2 = e2 * (uint32_t)sizeof(float2), vd2 = e2 * (uint32_t)sizeof(DT);
-    const O1 vs1 = e1 * (O1)sizeof(float2), vd1 = e1 * (O1)sizeof(DT);
+    const uint32_t vs2 = (lane_lo + (lane_hi << s4)) * (uint32_t)sizeof(float2), vd2 = e2 * (uint32_t)sizeof(DT);
+    const O1 vs1 = ((O1)lane_lo + ((O1)lane_hi << s8)) * (O1)sizeof(float2), vd1 = e1 * (O1)sizeof(DT);
     const uint64_t w2 = (uint64_t)wave << (a.pos4 + 2), w1 = (uint64_t)wave << (a.pos8 + 2);
+    const uint64_t sw2 = (uint64_t)wave << (s4 + 2), sw1 = (uint64_t)wave << (s8 + 2);
     const uint64_t psi_a = (uint64_t)(a.psi + (size_t)b * a.state_stride);
     const uint64_t lam_a = (uint64_t)(a.lam + (size_t)b * a.state_stride);
     const uint64_t diag_a = (uint64_t)a.diag;
@@ -631,9 +642,12 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         if constexpr (HIGH) base = tile_base(tile, a.pos4, a.pos8, a.w1, a.w2);
         else base = tile << kTileBits;
         // register strides, opaque per tile so their multiples are formed in scalar
-        // registers at each use rather than hoisted out of the loop
+        // registers at each use rather than hoisted out of the loop (rs: index, ss: state address)
         const uint64_t rs2 = opaque_u64(1ull << a.pos8), rs1 = opaque_u64(1ull << a.pos4);
         const uint64_t b2 = base + w2, b1 = base + w1;
+        const uint64_t sbase = K ? (base & ((1ull << K) - 1)) | ((base >> K) << (K + 1)) : base;
+        const uint64_t ss2 = opaque_u64(1ull << s8), ss1 = opaque_u64(1ull << s4);
+        const uint64_t sb2 = sbase + sw2, sb1 = sbase + sw1;
         RegQ *cq = (RegQ *)a.cq;
         // cost values of the thread's registers in layout 2 / layout 1: five loads of the diagonal, or
         // (TAB) the load of the tile's table row, with the values formed by cz_ready before their use
@@ -650,11 +664,11 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         auto cz_ready = [&](RegCost &rc) {
             if constexpr (TAB) reg_cost_form(rc, tv);
         };
-        auto ld2 = [&](uint64_t arr, int r) { return gld<float2>(arr + (b2 + r * rs2) * 8, vs2); };
+        auto ld2 = [&](uint64_t arr, int r) { return gld<float2>(arr + (sb2 + r * ss2) * 8, vs2); };
         // stores take their own opaque copy of the stride: sharing the load addresses
         // would keep 16-32 scalar address pairs live across the whole tile
-        auto st2f = [&](uint64_t arr, int r, float2 x, uint64_t rs) { gst(arr + (b2 + r * rs) * 8, vs2, x); };
-        auto st1f = [&](uint64_t arr, int r, float2 x, uint64_t rs) { gst(arr + (b1 + r * rs) * 8, vs1, x); };
+        auto st2f = [&](uint64_t arr, int r, float2 x, uint64_t ss) { gst(arr + (sb2 + r * ss) * 8, vs2, x); };
+        auto st1f = [&](uint64_t arr, int r, float2 x, uint64_t ss) { gst(arr + (sb1 + r * ss) * 8, vs1, x); };
 
         // passes that read the cost after a mixer issue those reads with the state loads, so they
         // are in flight during the mixer (the partitioned adjoint turn, at its register limit, and
@@ -682,7 +696,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             }
             double unused = 0.0;
             mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
-            const uint64_t rss = opaque_u64(rs1);
+            const uint64_t rss = opaque_u64(ss1);
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
         } else if constexpr (KIND == FK_MID || KIND == FK_TURN || KIND == FK_LAST) {
@@ -692,7 +706,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             double unused = 0.0;
             mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
             if constexpr (KIND == FK_MID) {
-                const uint64_t rss = opaque_u64(rs1);
+                const uint64_t rss = opaque_u64(ss1);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
             } else if constexpr (KIND == FK_TURN) {
@@ -712,7 +726,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     }
                 }
                 mix_op<HIGH, FULL, 1, 1, 1, false, FB2>(lds, v, t, a.active, c2, unused);
-                const uint64_t rss = opaque_u64(rs2);
+                const uint64_t rss = opaque_u64(ss2);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) st2f(psi_a, r, v[0][r], rss);
             } else {
@@ -727,7 +741,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 }
                 acc[0] += e;
                 if (a.store_psi) {
-                    const uint64_t rss = opaque_u64(rs1);
+                    const uint64_t rss = opaque_u64(ss1);
 #pragma unroll
                     for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
                 }
@@ -752,7 +766,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             acc[0] += e;
             mix_op<HIGH, FULL, 1, 2, 3, true, FB2>(lds, v, t, a.active, c2, gb);
             acc[1] += gb;
-            const uint64_t rss = opaque_u64(rs2);
+            const uint64_t rss = opaque_u64(ss2);
 #pragma unroll
             for (int r = 0; r < kRegs; ++r) st2f(lam_a, r, v[1][r], rss);
         } else {
@@ -770,7 +784,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             mix_op<HIGH, FULL, 2, 2, 3, true, FB1>(lds, v, t, a.active, c1, gb);
             acc[0] += gb;
             if constexpr (KIND == FK_BMID) {
-                const uint64_t rss = opaque_u64(rs1);
+                const uint64_t rss = opaque_u64(ss1);
 #pragma unroll
                 for (int r = 0; r < kRegs; ++r) {
                     st1f(psi_a, r, v[0][r], rss);
@@ -800,7 +814,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     double gb2 = 0.0;
                     mix_op<HIGH, FULL, 1, 2, 3, true, FB2>(lds, v, t, a.active, c2, gb2);
                     acc[2] += gb2;
-                    const uint64_t rss = opaque_u64(rs2);
+                    const uint64_t rss = opaque_u64(ss2);
 #pragma unroll
                     for (int r = 0; r < kRegs; ++r) {
                         st2f(psi_a, r, v[0][r], rss);
