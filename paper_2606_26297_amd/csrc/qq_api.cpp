@@ -473,7 +473,7 @@ int choose_G(int n, int B)
 // both states lie 512 KiB apart instead of a whole state array apart.  Measured at n = 28, p = 8,
 // 64 states: step 2262 ms with separate arrays, 2224 / 2214 / 2227 / 2253 ms with blocks of 2^12,
 // 2^16, 2^20, 2^24 amplitudes (the adjoint turn on the set {12..15, 24..27}: 105 ms apart, 96 ms
-// interleaved by 2^16).
+// interleaved by 2^16); n = 32 with four QPUs, partitioned: 592 -> 565 ms.
 constexpr int kIlvBit = 16;
 
 struct Layout {
@@ -491,10 +491,9 @@ Layout make_layout(const qq_problem *pb, int p, int B, int flags, const Plan &pl
     const size_t es = (flags & QQ_C128) ? 16 : 8;
     const bool grad = flags & QQ_GRAD;
     const bool multi = plan.sets.size() > 1;
-    // interleave where every pass is a complex64 per-pass kernel with monolithic phases, the state has
-    // more than one block, and no run of four qubits of a high set straddles bit kIlvBit (the low set's
-    // runs lie below it)
-    if (grad && multi && !(flags & (QQ_C128 | QQ_PARTITIONED)) && pb->n <= kFastMaxN && pb->n > kIlvBit) {
+    // interleave where every pass is a complex64 per-pass kernel, the state has more than one block,
+    // and no run of four qubits of a high set straddles bit kIlvBit (the low set's runs lie below it)
+    if (grad && multi && !(flags & QQ_C128) && pb->n <= kFastMaxN && pb->n > kIlvBit) {
         bool ok = true;
         for (const PassPlan &pp : plan.passes) ok = ok && pp.fkind >= 0;
         auto one_side = [](int q) { return q >= kIlvBit || q + 4 <= kIlvBit; };

@@ -614,8 +614,8 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
     using O1 = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
     // index offsets (the cost diagonal, the partitioned gathers) and state address offsets: with
     // interleaved psi / lambda blocks (a.ilv = K) a run of four qubits at q >= K sits at q + 1 (no run
-    // straddles K); partitioned evaluations keep separate arrays
-    const int K = PART ? 0 : a.ilv;
+    // straddles K)
+    const int K = a.ilv;
     const int s4 = a.pos4 + (K && a.pos4 >= K), s8 = a.pos8 + (K && a.pos8 >= K);
     const uint32_t e2 = lane_lo + (lane_hi << a.pos4);
     const O1 e1 = (O1)lane_lo + ((O1)lane_hi << a.pos8);
