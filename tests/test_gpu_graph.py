@@ -26,7 +26,8 @@ def _lib():
 
 
 CASES = [("regular3_n10_single_pass", 10, 2, 4, 0), ("regular3_n16_two_sets", 16, 3, 4, 0),
-         ("regular3_n22_partial_set", 22, 2, 2, 0), ("regular3_n12_c128", 12, 2, 2, N.QQ_C128)]
+         ("regular3_n22_partial_set", 22, 2, 2, 0), ("regular3_n12_c128", 12, 2, 2, N.QQ_C128),
+         ("regular3_n20_interleaved_psi_lambda", 20, 2, 2, 0)]
 
 
 @pytest.mark.parametrize("name,n,p,B,flags", CASES, ids=[c[0] for c in CASES])
