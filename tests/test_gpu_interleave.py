@@ -29,6 +29,9 @@ def c64_bound(n, sigma, gmax):
 
 @pytest.mark.parametrize("n,p,batch", [(20, 3, 3), (21, 2, 2), (26, 2, 2), (29, 2, 1), (31, 1, 1)])
 def test_interleaved_gradients_vs_complex128(n, p, batch):
+    import torch
+
+    torch.cuda.empty_cache()  # the library allocates its own workspaces here
     inst = W.dense_gaussian_upper(n, 600 + n)
     pb = Problem(inst.H, inst.f, inst.c0)
     try:
