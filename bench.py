@@ -337,7 +337,7 @@ def uneven_batch(dev, reps=5, pinned=None, persistent_only=False):
                "bound_holds": bool(all(gq[k] * np.max(np.abs(ref[k]["gradient"])) <= errb[k][0]
                                        for k in range(len(items)))),
                "note": "host inputs and outputs; the complex128 recomputations run as per-problem launches "
-                       "back to back on one workspace, read back with one synchronisation"}
+                       "spread over four streams with a workspace each, read back with one synchronisation"}
     vs_oracle = {"problems": len(items), "energy_rel_max": max(e_rel), "grad_rel_max": max(g_rel),
                  "grad_rel_median": float(np.median(g_rel)), "grad_rel_over_1e-5": int(sum(v > 1e-5 for v in g_rel)),
                  "grad_abs_over_sigma_max": max(g_abs),

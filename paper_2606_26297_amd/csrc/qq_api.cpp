@@ -1310,14 +1310,28 @@ struct C128Job {
     double *energy, *grad;  // host outputs, indexed by set
 };
 
-// Recompute every job's sets with complex128 states (host in, host out): the jobs share one workspace
-// (the largest any of them needs) and one device output buffer, run back to back on `stream` and are
-// read back with one synchronisation.  All problems are on one device.
+// Streams owned for the length of one call (default priority), destroyed on every return path.
+struct SideStreams {
+    std::vector<hipStream_t> s;
+    ~SideStreams()
+    {
+        for (hipStream_t x : s) (void)hipStreamDestroy(x);
+    }
+};
+
+// Recompute every job's sets with complex128 states (host in, host out).  The parameters go to the
+// device in one copy; the jobs then run round-robin on up to kC128Streams streams of their own, each
+// with its own workspace (the largest any job needs), so that the small per-problem launches of
+// different problems overlap; one device output buffer is read back after all of them.  All
+// problems are on one device.
+constexpr int kC128Streams = 4;
+
 qq_status recompute_c128(std::vector<C128Job> &jobs, int flags, void *stream_)
 {
     const int f = (flags & (QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED)) | QQ_C128;
     const bool grad = flags & QQ_GRAD;
     size_t wsmax = 0, nx = 0, nout = 0;
+    int nj = 0;
     for (const C128Job &j : jobs) {
         if (j.sets.empty()) continue;
         const int m = (int)j.sets.size();
@@ -1326,33 +1340,55 @@ qq_status recompute_c128(std::vector<C128Job> &jobs, int flags, void *stream_)
         wsmax = std::max(wsmax, w);
         nx += (size_t)m * 2 * j.p;
         nout += (size_t)m * (1 + (grad ? 2 * j.p : 0));
+        ++nj;
     }
-    if (nx == 0) return QQ_OK;
+    if (nj == 0) return QQ_OK;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const int device = jobs[0].pb->device;
     QQ_HIP(hipSetDevice(device));
-    if (qq_status st = check_device_fits(device, wsmax + nout * sizeof(double), "the complex128 recomputation");
-        st != QQ_OK)
-        return st;
-    DevBuf ws, out;
-    if (hipMalloc(&ws.p, wsmax) != hipSuccess || hipMalloc(&out.p, nout * sizeof(double)) != hipSuccess)
-        return fail(QQ_E_NOMEM, "hipMalloc of %zu + %zu bytes for the complex128 recomputation failed", wsmax,
-                    nout * sizeof(double));
-    double *d_out = static_cast<double *>(out.p);
+    const int ns = std::min(kC128Streams, nj);
+    const size_t wsa = align_up(wsmax);
+    const size_t need = (size_t)ns * wsa + (nx + nout) * sizeof(double);
+    if (qq_status st = check_device_fits(device, need, "the complex128 recomputation"); st != QQ_OK) return st;
+    DevBuf ws, buf;
+    if (hipMalloc(&ws.p, (size_t)ns * wsa) != hipSuccess || hipMalloc(&buf.p, (nx + nout) * sizeof(double)) != hipSuccess)
+        return fail(QQ_E_NOMEM, "hipMalloc of %zu bytes for the complex128 recomputation failed", need);
+    double *d_x = static_cast<double *>(buf.p), *d_out = d_x + nx;
     std::vector<double> x(nx), h(nout);
-    size_t xo = 0, oo = 0;
+    size_t xo = 0;
     for (const C128Job &j : jobs) {
         if (j.sets.empty()) continue;
         const int m = (int)j.sets.size(), w = 2 * j.p;
         for (int i = 0; i < m; ++i)
             std::memcpy(&x[xo + (size_t)i * w], j.params + (size_t)j.sets[i] * w, w * sizeof(double));
-        if (qq_status st = qq_evaluate(j.pb, j.p, m, &x[xo], f | QQ_OUT_ON_DEVICE, ws.p, wsmax, stream, d_out + oo,
-                                       grad ? d_out + oo + m : nullptr);
-            st != QQ_OK)
+        xo += (size_t)m * w;
+    }
+    QQ_HIP(hipMemcpyAsync(d_x, x.data(), nx * sizeof(double), hipMemcpyHostToDevice, stream));
+    QQ_HIP(hipStreamSynchronize(stream));
+    SideStreams side;
+    for (int k = 0; k < ns; ++k) {
+        hipStream_t sk = nullptr;
+        QQ_HIP(hipStreamCreateWithFlags(&sk, hipStreamNonBlocking));
+        side.s.push_back(sk);
+    }
+    xo = 0;
+    size_t oo = 0;
+    int q = 0;
+    for (const C128Job &j : jobs) {
+        if (j.sets.empty()) continue;
+        const int m = (int)j.sets.size(), w = 2 * j.p;
+        char *wq = static_cast<char *>(ws.p) + (size_t)(q % ns) * wsa;
+        if (qq_status st = qq_evaluate(j.pb, j.p, m, d_x + xo, f | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE, wq, wsmax,
+                                       side.s[q % ns], d_out + oo, grad ? d_out + oo + m : nullptr);
+            st != QQ_OK) {
+            for (hipStream_t sk : side.s) (void)hipStreamSynchronize(sk);
             return st;
+        }
         xo += (size_t)m * w;
         oo += (size_t)m * (1 + (grad ? w : 0));
+        ++q;
     }
+    for (hipStream_t sk : side.s) QQ_HIP(hipStreamSynchronize(sk));
     QQ_HIP(hipMemcpyAsync(h.data(), d_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream));
     QQ_HIP(hipStreamSynchronize(stream));
     oo = 0;
