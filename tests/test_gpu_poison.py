@@ -2,8 +2,9 @@
 float and double) before the evaluation's kernels run.  A kernel that read a workspace byte the call
 had not written first would turn its results into NaN or change them; the results must instead equal
 the unpoisoned ones bit for bit, for the complex64 specialised passes (energy and gradient), the
-generic complex128 and single-pass kernels, the persistent many-problem launch and the final state.
-Also checks QQ_LOG's one line per call."""
+generic complex128 and single-pass kernels, the persistent many-problem launch and the final state
+(n = 24 covers the interleaved psi / lambda region of gradient evaluations).  Also checks QQ_LOG's one
+line per call."""
 import os
 
 import numpy as np
@@ -35,8 +36,10 @@ def run_all(pbs, xs):
 
 
 def test_poisoned_workspaces_change_nothing(monkeypatch):
-    insts = [W.dense_integer_symmetric(10, 501), W.regular_graph_qubo(18, 502), W.dense_gaussian_upper(21, 503)]
-    xs = [W.random_params(p, 3, 510 + p) for p in (2, 3, 2)]
+    # n = 24: gradients with psi and lambda interleaved in one region
+    insts = [W.dense_integer_symmetric(10, 501), W.regular_graph_qubo(18, 502), W.dense_gaussian_upper(21, 503),
+             W.regular_graph_qubo(24, 511)]
+    xs = [W.random_params(p, 3, 510 + p) for p in (2, 3, 2, 2)]
     pbs = [Problem(i.H, i.f, i.c0) for i in insts]
     try:
         monkeypatch.delenv("QQ_POISON", raising=False)
