@@ -68,6 +68,43 @@ __device__ __forceinline__ void gst(uint64_t sbase, O voff, float2 x)
     const uint64_t u = (uint64_t)__float_as_uint(x.x) | ((uint64_t)__float_as_uint(x.y) << 32);
     __builtin_nontemporal_store(u, reinterpret_cast<uint64_t __attribute__((address_space(1))) *>(sbase + voff));
 }
+
+// Two registers through one 16-byte access per lane.  In the thread layouts qubit 0 is lane bit 0, so
+// the two lanes of a lane pair hold neighbouring amplitudes: for registers (r, r + 1) the even lane
+// accesses register r's amplitudes z and z + 1, the odd lane register r + 1's, and one swap of 8 bytes
+// between the two lanes gives each lane its own two values (loads) or the pair its 16 bytes (stores).
+// Half the address work and wider transfers for the same bytes.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t lane_swap(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xb1, 0xf, 0xf, false);  // quad_perm [1, 0, 3, 2]
+}
+
+template <typename O>
+__device__ __forceinline__ void gld_pair(uint64_t sbase, O voff, uint32_t odd, float2 &lo, float2 &hi)
+{
+    const u32x4 l =
+        __builtin_nontemporal_load(reinterpret_cast<const u32x4 __attribute__((address_space(1))) *>(sbase + voff));
+    // even lane: (r at z, r at z + 1), keeps the first, sends the second; odd lane: (r + 1 at z - 1, r + 1
+    // at z), keeps the second, sends the first
+    const uint32_t rx = lane_swap(odd ? l.x : l.z), ry = lane_swap(odd ? l.y : l.w);
+    lo = odd ? make_float2(__uint_as_float(rx), __uint_as_float(ry)) : make_float2(__uint_as_float(l.x), __uint_as_float(l.y));
+    hi = odd ? make_float2(__uint_as_float(l.z), __uint_as_float(l.w)) : make_float2(__uint_as_float(rx), __uint_as_float(ry));
+}
+
+template <typename O>
+__device__ __forceinline__ void gst_pair(uint64_t sbase, O voff, uint32_t odd, float2 lo, float2 hi)
+{
+    const float2 snd = odd ? lo : hi;
+    const uint32_t rx = lane_swap(__float_as_uint(snd.x)), ry = lane_swap(__float_as_uint(snd.y));
+    u32x4 o;
+    o.x = odd ? rx : __float_as_uint(lo.x);
+    o.y = odd ? ry : __float_as_uint(lo.y);
+    o.z = odd ? __float_as_uint(hi.x) : rx;
+    o.w = odd ? __float_as_uint(hi.y) : ry;
+    __builtin_nontemporal_store(o, reinterpret_cast<u32x4 __attribute__((address_space(1))) *>(sbase + voff));
+}
 // A wave-uniform value the optimiser must treat as unknown at this point (keeps
 // uses inside the loop).  The read-first-lane is free for a value already in
 // scalar registers and makes the scalar constraint legal where the compiler
@@ -623,6 +660,16 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
     const O1 vs1 = ((O1)lane_lo + ((O1)lane_hi << s8)) * (O1)sizeof(float2), vd1 = e1 * (O1)sizeof(DT);
     const uint64_t w2 = (uint64_t)wave << (a.pos4 + 2), w1 = (uint64_t)wave << (a.pos8 + 2);
     const uint64_t sw2 = (uint64_t)wave << (s4 + 2), sw1 = (uint64_t)wave << (s8 + 2);
+    // PAIR: state accesses by register pairs (gld_pair / gst_pair); the odd lane's offset is the even
+    // lane's plus one register stride (layout 2: registers at s8, layout 1: at s4), within 32 bits
+    // wherever the lane offsets are (not WIDE).  Measured at n = 28, B = 64: mid 45.2 -> 43.7 ms,
+    // adjoint mid 90.7 -> 87.8, last with the seed 52.0 -> 50.5, but the adjoint turn on the high sets
+    // 94.0 / 95.4 -> 99 / 102.5 and the turn mixed (one set faster, one slower): so the 12-qubit set's
+    // passes and the last pass take them, the other high-set passes keep 8-byte accesses
+    constexpr bool PAIR = !WIDE && !PART && (!HIGH || KIND == FK_LASTG);
+    const uint32_t odd = PAIR ? lane_lo & 1u : 0u;
+    const uint32_t pv2 = PAIR ? vs2 - 8u * odd + odd * (uint32_t)(8ull << s8) : 0u;
+    const O1 pv1 = PAIR ? vs1 - (O1)(8u * odd) + (O1)odd * (O1)(8ull << s4) : (O1)0;
     const uint64_t psi_a = (uint64_t)(a.psi + (size_t)b * a.state_stride);
     const uint64_t lam_a = (uint64_t)(a.lam + (size_t)b * a.state_stride);
     const uint64_t diag_a = (uint64_t)a.diag;
@@ -669,6 +716,80 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
         // would keep 16-32 scalar address pairs live across the whole tile
         auto st2f = [&](uint64_t arr, int r, float2 x, uint64_t ss) { gst(arr + (sb2 + r * ss) * 8, vs2, x); };
         auto st1f = [&](uint64_t arr, int r, float2 x, uint64_t ss) { gst(arr + (sb1 + r * ss) * 8, vs1, x); };
+        // all 16 registers of one state: loads in layout 2, stores in layout 2 / layout 1
+        auto ld2all = [&](uint64_t arr, float2 (&x)[kRegs]) {
+            if constexpr (PAIR) {
+#pragma unroll
+                for (int q = 0; q < kRegs; q += 2) gld_pair(arr + (sb2 + q * ss2) * 8, pv2, odd, x[q], x[q + 1]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) x[r] = ld2(arr, r);
+            }
+        };
+        auto st2all = [&](uint64_t arr, const float2 (&x)[kRegs], uint64_t ss) {
+            if constexpr (PAIR) {
+#pragma unroll
+                for (int q = 0; q < kRegs; q += 2) gst_pair(arr + (sb2 + q * ss) * 8, pv2, odd, x[q], x[q + 1]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) st2f(arr, r, x[r], ss);
+            }
+        };
+        // psi and lambda together, register by register (pairs of registers with PAIR)
+        auto ld2both = [&](float2 (&x)[kRegs], float2 (&y)[kRegs]) {
+            if constexpr (PAIR) {
+#pragma unroll
+                for (int q = 0; q < kRegs; q += 2) {
+                    gld_pair(psi_a + (sb2 + q * ss2) * 8, pv2, odd, x[q], x[q + 1]);
+                    gld_pair(lam_a + (sb2 + q * ss2) * 8, pv2, odd, y[q], y[q + 1]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) {
+                    x[r] = ld2(psi_a, r);
+                    y[r] = ld2(lam_a, r);
+                }
+            }
+        };
+        auto st2both = [&](const float2 (&x)[kRegs], const float2 (&y)[kRegs], uint64_t ss) {
+            if constexpr (PAIR) {
+#pragma unroll
+                for (int q = 0; q < kRegs; q += 2) {
+                    gst_pair(psi_a + (sb2 + q * ss) * 8, pv2, odd, x[q], x[q + 1]);
+                    gst_pair(lam_a + (sb2 + q * ss) * 8, pv2, odd, y[q], y[q + 1]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) {
+                    st2f(psi_a, r, x[r], ss);
+                    st2f(lam_a, r, y[r], ss);
+                }
+            }
+        };
+        auto st1both = [&](const float2 (&x)[kRegs], const float2 (&y)[kRegs], uint64_t ss) {
+            if constexpr (PAIR) {
+#pragma unroll
+                for (int q = 0; q < kRegs; q += 2) {
+                    gst_pair(psi_a + (sb1 + q * ss) * 8, pv1, odd, x[q], x[q + 1]);
+                    gst_pair(lam_a + (sb1 + q * ss) * 8, pv1, odd, y[q], y[q + 1]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) {
+                    st1f(psi_a, r, x[r], ss);
+                    st1f(lam_a, r, y[r], ss);
+                }
+            }
+        };
+        auto st1all = [&](uint64_t arr, const float2 (&x)[kRegs], uint64_t ss) {
+            if constexpr (PAIR) {
+#pragma unroll
+                for (int q = 0; q < kRegs; q += 2) gst_pair(arr + (sb1 + q * ss) * 8, pv1, odd, x[q], x[q + 1]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRegs; ++r) st1f(arr, r, x[r], ss);
+            }
+        };
 
         // passes that read the cost after a mixer issue those reads with the state loads, so they
         // are in flight during the mixer (the partitioned adjoint turn, at its register limit, and
@@ -697,18 +818,15 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             double unused = 0.0;
             mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
             const uint64_t rss = opaque_u64(ss1);
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
+            st1all(psi_a, v[0], rss);
         } else if constexpr (KIND == FK_MID || KIND == FK_TURN || KIND == FK_LAST) {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) v[0][r] = ld2(psi_a, r);
+            ld2all(psi_a, v[0]);
             if constexpr (EARLY) cz1(rc);
             double unused = 0.0;
             mix_op<HIGH, FULL, 2, 1, 1, false, FB1>(lds, v, t, a.active, c1, unused);
             if constexpr (KIND == FK_MID) {
                 const uint64_t rss = opaque_u64(ss1);
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
+                st1all(psi_a, v[0], rss);
             } else if constexpr (KIND == FK_TURN) {
                 if constexpr (PART) {
                     float uf[kRegs];
@@ -727,8 +845,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 }
                 mix_op<HIGH, FULL, 1, 1, 1, false, FB2>(lds, v, t, a.active, c2, unused);
                 const uint64_t rss = opaque_u64(ss2);
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) st2f(psi_a, r, v[0][r], rss);
+                st2all(psi_a, v[0], rss);
             } else {
                 double e = 0.0;
                 if constexpr (!EARLY) cz1(rc);
@@ -742,13 +859,11 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                 acc[0] += e;
                 if (a.store_psi) {
                     const uint64_t rss = opaque_u64(ss1);
-#pragma unroll
-                    for (int r = 0; r < kRegs; ++r) st1f(psi_a, r, v[0][r], rss);
+                    st1all(psi_a, v[0], rss);
                 }
             }
         } else if constexpr (KIND == FK_LASTG) {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) v[0][r] = ld2(psi_a, r);
+            ld2all(psi_a, v[0]);
             if constexpr (EARLY) cz1(rc);
             double gb = 0.0;
             mix_op<HIGH, FULL, 2, 2, 1, false, FB1>(lds, v, t, a.active, c1, gb);
@@ -767,29 +882,20 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
             mix_op<HIGH, FULL, 1, 2, 3, true, FB2>(lds, v, t, a.active, c2, gb);
             acc[1] += gb;
             const uint64_t rss = opaque_u64(ss2);
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) st2f(lam_a, r, v[1][r], rss);
+            st2all(lam_a, v[1], rss);
         } else {
             // partitioned adjoint turn: the un-phase angles (layout 1) before any amplitude is live
             float uf_b[kRegs];
             if constexpr (KIND == FK_BTURN && PART)
                 part_angles<DT>(uf_b, a, g2pi, b1, lane_lo, lane_hi, a.pos8, a.pos4, tile, t);
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) {
-                v[0][r] = ld2(psi_a, r);
-                v[1][r] = ld2(lam_a, r);
-            }
+            ld2both(v[0], v[1]);
             if constexpr (EARLY) cz1(rc);
             double gb = 0.0;
             mix_op<HIGH, FULL, 2, 2, 3, true, FB1>(lds, v, t, a.active, c1, gb);
             acc[0] += gb;
             if constexpr (KIND == FK_BMID) {
                 const uint64_t rss = opaque_u64(ss1);
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) {
-                    st1f(psi_a, r, v[0][r], rss);
-                    st1f(lam_a, r, v[1][r], rss);
-                }
+                st1both(v[0], v[1], rss);
             } else {
                 double gg = 0.0;
                 if constexpr (!EARLY) cz1(rc);
@@ -815,11 +921,7 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
                     mix_op<HIGH, FULL, 1, 2, 3, true, FB2>(lds, v, t, a.active, c2, gb2);
                     acc[2] += gb2;
                     const uint64_t rss = opaque_u64(ss2);
-#pragma unroll
-                    for (int r = 0; r < kRegs; ++r) {
-                        st2f(psi_a, r, v[0][r], rss);
-                        st2f(lam_a, r, v[1][r], rss);
-                    }
+                    st2both(v[0], v[1], rss);
                 }
             }
         }
