@@ -203,10 +203,10 @@ __device__ __forceinline__ void run_geom(int geom, const FastArgs &a, float2 *ld
                                          int g)
 {
     if (geom == 0) {
-        run_pass<KIND, false, true, DT, false, false, true>(a, lds, acc, t, b, g);
+        run_pass<KIND, false, true, DT, false, false, true, false>(a, lds, acc, t, b, g);
     } else if constexpr (KIND != FK_FIRST) {  // the persistent plans take the qubit-0..11 set first
-        if (geom == 1) run_pass<KIND, true, true, DT, false, false, true>(a, lds, acc, t, b, g);
-        else run_pass<KIND, true, false, DT, false, false, true>(a, lds, acc, t, b, g);
+        if (geom == 1) run_pass<KIND, true, true, DT, false, false, true, false>(a, lds, acc, t, b, g);
+        else run_pass<KIND, true, false, DT, false, false, true, false>(a, lds, acc, t, b, g);
     }
 }
 

@@ -633,7 +633,7 @@ constexpr int kind_slots()
 }
 
 // The tile loop of one pass kind.  FB1 / FB2: form of the first / second mixer coefficient.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool WIDE, bool FB1, bool FB2, bool CT>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART, bool WIDE, bool FB1, bool FB2, bool CT, bool PR>
 __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g,
                                           const MixCoef &c1, const MixCoef &c2, double g2pi)
 {
@@ -665,8 +665,9 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
     // wherever the lane offsets are (not WIDE).  Measured at n = 28, B = 64: mid 45.2 -> 43.7 ms,
     // adjoint mid 90.7 -> 87.8, last with the seed 52.0 -> 50.5, but the adjoint turn on the high sets
     // 94.0 / 95.4 -> 99 / 102.5 and the turn mixed (one set faster, one slower): so the 12-qubit set's
-    // passes and the last pass take them, the other high-set passes keep 8-byte accesses
-    constexpr bool PAIR = !WIDE && !PART && (!HIGH || KIND == FK_LASTG);
+    // passes and the last pass take them, the other high-set passes keep 8-byte accesses.  PR = false:
+    // never (the persistent launch: 22.0 -> 23.2 ms on the uneven batch with them)
+    constexpr bool PAIR = PR && !WIDE && !PART && (!HIGH || KIND == FK_LASTG);
     const uint32_t odd = PAIR ? lane_lo & 1u : 0u;
     const uint32_t pv2 = PAIR ? vs2 - 8u * odd + odd * (uint32_t)(8ull << s8) : 0u;
     const O1 pv1 = PAIR ? vs1 - (O1)(8u * odd) + (O1)odd * (O1)(8ull << s4) : (O1)0;
@@ -931,7 +932,8 @@ __device__ __forceinline__ void pass_body(const FastArgs &a, float2 *lds, double
 // Layer constants of one pass for parameter set x, then one uniform dispatch on
 // the forms of the (up to two) mixer coefficients, so the butterfly code of each
 // path has no form branch.  Tiles g, g + a.G, ... below a.tiles.
-template <int KIND, bool HIGH, bool FULL, typename DT, bool PART = false, bool WIDE = false, bool CT = false>
+template <int KIND, bool HIGH, bool FULL, typename DT, bool PART = false, bool WIDE = false, bool CT = false,
+          bool PR = true>
 __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double (&acc)[3], int t, int b, int g)
 {
     const double *x = a.params + (size_t)b * 2 * a.p;
@@ -960,15 +962,15 @@ __device__ __forceinline__ void run_pass(const FastArgs &a, float2 *lds, double 
     constexpr bool TWO = KIND == FK_TURN || KIND == FK_LASTG || KIND == FK_BTURN;
     if constexpr (!FULL) {
         // general butterflies: one body serves both forms
-        pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false, CT, PR>(a, lds, acc, t, b, g, c1, c2, g2pi);
         return;
     }
     const int sel = (c1.formB ? 1 : 0) | (TWO && c2.formB ? 2 : 0);
-    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
-    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, false, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    if (sel == 0) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, false, CT, PR>(a, lds, acc, t, b, g, c1, c2, g2pi);
+    else if (sel == 1) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, false, CT, PR>(a, lds, acc, t, b, g, c1, c2, g2pi);
     else if constexpr (TWO) {
-        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, true, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
-        else pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, true, CT>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        if (sel == 2) pass_body<KIND, HIGH, FULL, DT, PART, WIDE, false, true, CT, PR>(a, lds, acc, t, b, g, c1, c2, g2pi);
+        else pass_body<KIND, HIGH, FULL, DT, PART, WIDE, true, true, CT, PR>(a, lds, acc, t, b, g, c1, c2, g2pi);
     }
 }
 
