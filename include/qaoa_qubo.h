@@ -201,27 +201,29 @@ qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int 
  * QQ_PARAMS_ON_DEVICE) into energy_out[i] (batch[i] doubles) and, with
  * QQ_GRAD, grad_out[i] (batch[i] x 2p[i]); host memory unless
  * QQ_OUT_ON_DEVICE.  Same results as qq_evaluate on each problem, up to the
- * order of the FP64 partial sums (complex64 state, FP64 diagonal, phase
- * reduction and accumulators).
+ * order of the FP64 partial sums (complex64 state, or complex128 with
+ * QQ_C128; FP64 diagonal, phase reduction and accumulators).
  *
  * Execution: one launch per cost-diagonal element type present (at most
  * three) drains a queue of (problem, parameter set, pass, tile chunk) items in
  * level-major order from an atomic ticket; a problem with n <= 12 is one item
- * per parameter set.  Items of a pass wait, bounded in time, for the previous
+ * per parameter set.  With QQ_C128 the items run the general complex128 pass
+ * bodies of qq_evaluate (every problem by tile chunks; for n <= 12 one item of
+ * one tile).  Items of a pass wait, bounded in time, for the previous
  * pass on the same state; a wait longer than opt->wait_limit_ms sets a device
  * flag, the launch drains early and the call returns QQ_E_DEVICE.  The call
  * synchronises the stream before returning (it reads that flag).
  *
  * Limits: every problem on one device, n <= 31, 1 <= p <= QQ_MAX_P,
- * batch >= 1.  QQ_C128 and QQ_PARTITIONED are not served here
- * (QQ_E_UNSUPPORTED; use qq_evaluate).
+ * batch >= 1.  QQ_PARTITIONED is not served here (QQ_E_UNSUPPORTED; use
+ * qq_evaluate).
  * workspace: device buffer of ws_bytes >= qq_workspace_size_many(), or NULL
  * to let the library allocate one for this call.  opt may be NULL (defaults).
  * Errors: QQ_E_INVALID, QQ_E_UNSUPPORTED, QQ_E_WORKSPACE, QQ_E_TOO_LARGE,
  * QQ_E_NOMEM, QQ_E_DEVICE.
  */
 typedef struct {
-    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: 16 */
+    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: 16 (QQ_C128: 4) */
     int max_workgroups;    /* cap on the persistent grid; 0: every workgroup that fits on the device at once */
     double wait_limit_ms;  /* bound on one dependency wait; 0: 2000 ms */
 } qq_many_options;
@@ -300,9 +302,9 @@ qq_status qq_evaluate_guarded(qq_problem *prob, int p, int batch, const double *
                               double *grad_err_out);
 
 /* The same for many problems: complex64 through one persistent launch (qq_evaluate_many), then the
- * sets whose bound exceeds the tolerance through qq_evaluate with complex128 states, problem by
- * problem.  c128_out[i] and grad_err_out[i] (each array may be NULL, or hold NULL entries) have
- * batch[i] entries.  QQ_C128 and QQ_PARTITIONED are not accepted (as for qq_evaluate_many). */
+ * sets whose bound exceeds the tolerance through a second one with complex128 states (QQ_C128).
+ * c128_out[i] and grad_err_out[i] (each array may be NULL, or hold NULL entries) have batch[i]
+ * entries.  QQ_C128 and QQ_PARTITIONED are not accepted (QQ_E_UNSUPPORTED). */
 qq_status qq_evaluate_many_guarded(int count, qq_problem *const *problems, const int *p, const int *batch,
                                    const double *const *params, int flags, const qq_many_options *opt, double tol,
                                    void *stream, double *const *energy_out, double *const *grad_out,

@@ -876,6 +876,7 @@ struct ManyGroup {
     std::vector<int> members;  // problem indices, in queue priority order
     std::vector<ManyInst> inst;
     std::vector<ManyPass> pass;
+    std::vector<PassArgs> gpass;  // complex128: the general pass of each entry of `pass`
     std::vector<ManySeg> seg;
     std::vector<uint16_t> slot_out;
     uint32_t total = 0;
@@ -885,7 +886,7 @@ struct ManyGroup {
     double bytes = 0;  // algorithmic HBM bytes of the launch
     // workspace offsets
     size_t ctl = 0, desc = 0, partial = 0, states = 0;
-    size_t inst_off = 0, pass_off = 0, seg_off = 0, slot_off = 0, desc_bytes = 0;
+    size_t inst_off = 0, pass_off = 0, gpass_off = 0, seg_off = 0, slot_off = 0, desc_bytes = 0;
 };
 
 struct ManyLayout {
@@ -1087,13 +1088,15 @@ uint64_t fnv1a(uint64_t h, int64_t v)
     return h;
 }
 
-int many_tiles_per_chunk(uint64_t tiles, const qq_many_options *opt)
+int many_tiles_per_chunk(uint64_t tiles, const qq_many_options *opt, bool c128)
 {
     // 16 tiles (512 KiB of one complex64 state) per item: each item ends with an XCD-wide
     // cache write-back and two device-scope atomics, which a 16-tile item amortises,
     // while a 2^22-amplitude pass still splits into 64 items (measured on MI355X with
-    // the 512-problem uneven batch: 1 tile 107 ms, 8 tiles 30 ms, 16 and 32 tiles 25 ms)
-    const uint64_t want = (opt && opt->tiles_per_chunk > 0) ? (uint64_t)opt->tiles_per_chunk : 16;
+    // the 512-problem uneven batch: 1 tile 107 ms, 8 tiles 30 ms, 16 and 32 tiles 25 ms).
+    // Complex128 (one resident workgroup per compute unit): 4 tiles, so that the batch's
+    // longest chains split finely (its 88 flagged sets: 4 tiles 11.3 ms, 16 11.7, 64 25.5)
+    const uint64_t want = (opt && opt->tiles_per_chunk > 0) ? (uint64_t)opt->tiles_per_chunk : (c128 ? 4 : 16);
     return (int)std::min<uint64_t>(want, tiles);
 }
 
@@ -1101,6 +1104,7 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
                     const qq_many_options *opt, ManyLayout &M)
 {
     const bool grad = flags & QQ_GRAD;
+    const bool c128 = flags & QQ_C128;
     const int mode = plan_mode(flags | QQ_ENERGY, false);
     // problem order inside each level: longest pass chain first, then most tiles
     std::vector<int> order(count);
@@ -1156,7 +1160,57 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
             I.pass_off = (int)G.pass.size();
             I.slot_off = (int)G.slot_out.size();
             I.partial_off = G.partial_doubles;
-            if (plan.sets.size() == 1) {
+            if (c128) {
+                // complex128: the general pass bodies, chunks of tiles for every problem (one pass of
+                // one tile for n <= 12); the passes accumulate with C itself (shift 0)
+                I.tpc = many_tiles_per_chunk(I.tiles, opt, c128);
+                I.nchunks = (int)((I.tiles + (uint64_t)I.tpc - 1) / (uint64_t)I.tpc);
+                I.npasses = (int)plan.passes.size();
+                int slot_base = 0;
+                for (const PassPlan &pp : plan.passes) {
+                    const SetDesc &sd = plan.sets[pp.set];
+                    if ((int)pp.ops.size() > kMaxOps)
+                        return fail(QQ_E_UNSUPPORTED, "pass has %zu ops (max %d)", pp.ops.size(), kMaxOps);
+                    ManyPass P;
+                    std::memset(&P, 0, sizeof P);
+                    P.kind = -1;
+                    P.geom = pp.nstates;
+                    P.slot_base = slot_base;
+                    P.nslots = (int)pp.slot_out.size();
+                    PassArgs a;
+                    std::memset(&a, 0, sizeof a);
+                    a.n = pb->n;
+                    a.p = I.p;
+                    a.B = I.B;
+                    a.G = 1;
+                    a.tiles = I.tiles;
+                    a.dim_mask = I.dim_mask;
+                    a.pos4 = sd.pos4;
+                    a.pos8 = sd.pos8;
+                    a.high = sd.high;
+                    a.w1 = sd.pos4 - 4;
+                    a.w2 = sd.pos8 - sd.pos4 - 4;
+                    a.flags = pp.flags;
+                    a.nops = (int)pp.ops.size();
+                    a.nslots = P.nslots;
+                    a.amp0 = I.amp0;
+                    a.state_stride = pb->dim;  // params, diag, psi, lam: device addresses, set at launch
+                    for (size_t o = 0; o < pp.ops.size(); ++o) a.ops[o] = pp.ops[o];
+                    slot_base += P.nslots;
+                    for (int o : pp.slot_out) G.slot_out.push_back((uint16_t)o);
+                    G.pass.push_back(P);
+                    G.gpass.push_back(a);
+                    G.bytes += pass_bytes(pb, pp, I.B, true, false);
+                }
+                I.nslots = slot_base;
+                const size_t sb = (size_t)pb->dim * 16 * I.B;
+                I.psi = reinterpret_cast<void *>(state_off);  // relative; fixed up at launch
+                state_off += align_up(sb);
+                if (grad) {
+                    I.lam = reinterpret_cast<void *>(state_off);
+                    state_off += align_up(sb);
+                }
+            } else if (plan.sets.size() == 1) {
                 // the whole evaluation in one item per parameter set; slot o is output o
                 ManyPass P;
                 std::memset(&P, 0, sizeof P);
@@ -1173,7 +1227,7 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
                 G.bytes += (double)pb->dim * diag_bytes_of(pb->diag_type);
             } else {
                 I.shift = pb->alpha;  // the pass bodies accumulate with C - alpha
-                I.tpc = many_tiles_per_chunk(I.tiles, opt);
+                I.tpc = many_tiles_per_chunk(I.tiles, opt, c128);
                 I.nchunks = (int)((I.tiles + (uint64_t)I.tpc - 1) / (uint64_t)I.tpc);
                 I.npasses = (int)plan.passes.size();
                 int slot_base = 0;
@@ -1234,7 +1288,8 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
         off += align_up((size_t)(2 + G.nstates) * sizeof(uint32_t));
         G.inst_off = 0;
         G.pass_off = align_up(G.inst.size() * sizeof(ManyInst), 16);
-        G.seg_off = G.pass_off + align_up(G.pass.size() * sizeof(ManyPass), 16);
+        G.gpass_off = G.pass_off + align_up(G.pass.size() * sizeof(ManyPass), 16);
+        G.seg_off = G.gpass_off + align_up(G.gpass.size() * sizeof(PassArgs), 16);
         G.slot_off = G.seg_off + align_up(G.seg.size() * sizeof(ManySeg), 16);
         G.desc_bytes = G.slot_off + G.slot_out.size() * sizeof(uint16_t);
         G.desc = off;
@@ -1253,10 +1308,10 @@ qq_status validate_many(int count, qq_problem *const *pbs, const int *p, const i
 {
     if (count < 1) return fail(QQ_E_INVALID, "count = %d must be >= 1", count);
     if (!pbs || !p || !batch) return fail(QQ_E_INVALID, "problems / p / batch is NULL");
-    const int known = QQ_ENERGY | QQ_GRAD | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE;
-    if (flags & (QQ_C128 | QQ_PARTITIONED))
-        return fail(QQ_E_UNSUPPORTED, "qq_evaluate_many runs complex64 monolithic evaluations only "
-                                      "(use qq_evaluate for QQ_C128 / QQ_PARTITIONED)");
+    const int known = QQ_ENERGY | QQ_GRAD | QQ_C128 | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE;
+    if (flags & QQ_PARTITIONED)
+        return fail(QQ_E_UNSUPPORTED, "qq_evaluate_many runs monolithic evaluations only "
+                                      "(use qq_evaluate for QQ_PARTITIONED)");
     if (flags & ~known) return fail(QQ_E_INVALID, "unknown flag bits 0x%x", flags & ~known);
     for (int i = 0; i < count; ++i) {
         if (!pbs[i]) return fail(QQ_E_INVALID, "problems[%d] is NULL", i);
@@ -1319,17 +1374,62 @@ struct SideStreams {
     }
 };
 
-// Recompute every job's sets with complex128 states (host in, host out).  The parameters go to the
-// device in one copy; the jobs then run round-robin on up to kC128Streams streams of their own, each
-// with its own workspace (the largest any job needs), so that the small per-problem launches of
-// different problems overlap; one device output buffer is read back after all of them.  All
-// problems are on one device.
+// Recompute every job's sets with complex128 states (host in, host out; all problems on one device).
+// Monolithic phases: one persistent complex128 launch (qq_evaluate_many) over all of them.
+// Partitioned phases: the parameters go to the device in one copy; the jobs then run round-robin on
+// up to kC128Streams streams of their own, each with its own workspace (the largest any job needs),
+// so that the small per-problem launches of different problems overlap; one device output buffer is
+// read back after all of them.
 constexpr int kC128Streams = 4;
 
 qq_status recompute_c128(std::vector<C128Job> &jobs, int flags, void *stream_)
 {
     const int f = (flags & (QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED)) | QQ_C128;
     const bool grad = flags & QQ_GRAD;
+    if (!(f & QQ_PARTITIONED)) {
+        // every recomputed set in one persistent complex128 launch (per cost-diagonal element type)
+        std::vector<qq_problem *> pbs;
+        std::vector<int> ps, bs;
+        std::vector<std::vector<double>> xs, es, gs;
+        std::vector<C128Job *> owner;
+        for (C128Job &j : jobs) {
+            if (j.sets.empty()) continue;
+            const int m = (int)j.sets.size(), w = 2 * j.p;
+            pbs.push_back(j.pb);
+            ps.push_back(j.p);
+            bs.push_back(m);
+            std::vector<double> x((size_t)m * w);
+            for (int i = 0; i < m; ++i)
+                std::memcpy(&x[(size_t)i * w], j.params + (size_t)j.sets[i] * w, w * sizeof(double));
+            xs.push_back(std::move(x));
+            es.emplace_back(m);
+            gs.emplace_back(grad ? (size_t)m * w : 0);
+            owner.push_back(&j);
+        }
+        if (pbs.empty()) return QQ_OK;
+        const int count = (int)pbs.size();
+        std::vector<const double *> xp(count);
+        std::vector<double *> ep(count), gp(count);
+        for (int q = 0; q < count; ++q) {
+            xp[q] = xs[q].data();
+            ep[q] = es[q].data();
+            gp[q] = grad ? gs[q].data() : nullptr;
+        }
+        if (qq_status st = qq_evaluate_many(count, pbs.data(), ps.data(), bs.data(), xp.data(), f, nullptr, nullptr, 0,
+                                            stream_, ep.data(), grad ? gp.data() : nullptr);
+            st != QQ_OK)
+            return st;
+        for (int q = 0; q < count; ++q) {
+            C128Job &j = *owner[q];
+            const int w = 2 * j.p;
+            for (size_t i = 0; i < j.sets.size(); ++i) {
+                j.energy[j.sets[i]] = es[q][i];
+                if (grad) std::memcpy(j.grad + (size_t)j.sets[i] * w, &gs[q][i * w], w * sizeof(double));
+            }
+        }
+        return QQ_OK;
+    }
+    // partitioned phases: per-problem evaluations spread over side streams
     size_t wsmax = 0, nx = 0, nout = 0;
     int nj = 0;
     for (const C128Job &j : jobs) {
@@ -2228,6 +2328,7 @@ static qq_status evaluate_many_impl(int count, qq_problem *const *problems, cons
     g_err.clear();
     if (qq_status st = validate_many(count, problems, p, batch, flags); st != QQ_OK) return st;
     const bool grad = flags & QQ_GRAD;
+    const bool c128 = flags & QQ_C128;
     if (!params || !energy_out || (grad && !grad_out)) return fail(QQ_E_INVALID, "params / energy_out / grad_out is NULL");
     for (int i = 0; i < count; ++i) {
         if (!params[i]) return fail(QQ_E_INVALID, "params[%d] is NULL", i);
@@ -2282,6 +2383,15 @@ static qq_status evaluate_many_impl(int count, qq_problem *const *problems, cons
                 I.psi = ws + G.states + reinterpret_cast<size_t>(I.psi);
                 I.lam = grad ? ws + G.states + reinterpret_cast<size_t>(I.lam) : nullptr;
             }
+            if (!G.gpass.empty()) {
+                for (int j = I.pass_off; j < I.pass_off + I.npasses; ++j) {
+                    PassArgs &a = G.gpass[j];
+                    a.params = I.params;
+                    a.diag = I.diag;
+                    a.psi = I.psi;
+                    a.lam = I.lam;
+                }
+            }
             if (flags & QQ_OUT_ON_DEVICE) {
                 I.energy_out = energy_out[i];
                 I.grad_out = grad ? grad_out[i] : nullptr;
@@ -2296,6 +2406,8 @@ static qq_status evaluate_many_impl(int count, qq_problem *const *problems, cons
         blob.assign(G.desc_bytes, 0);
         std::memcpy(blob.data() + G.inst_off, G.inst.data(), G.inst.size() * sizeof(ManyInst));
         std::memcpy(blob.data() + G.pass_off, G.pass.data(), G.pass.size() * sizeof(ManyPass));
+        if (!G.gpass.empty())
+            std::memcpy(blob.data() + G.gpass_off, G.gpass.data(), G.gpass.size() * sizeof(PassArgs));
         std::memcpy(blob.data() + G.seg_off, G.seg.data(), G.seg.size() * sizeof(ManySeg));
         std::memcpy(blob.data() + G.slot_off, G.slot_out.data(), G.slot_out.size() * sizeof(uint16_t));
         QQ_HIP(hipMemcpyAsync(ws + G.desc, blob.data(), G.desc_bytes, hipMemcpyHostToDevice, stream));
@@ -2305,6 +2417,7 @@ static qq_status evaluate_many_impl(int count, qq_problem *const *problems, cons
         ManyArgs a;
         a.inst = reinterpret_cast<const ManyInst *>(ws + G.desc + G.inst_off);
         a.pass = reinterpret_cast<const ManyPass *>(ws + G.desc + G.pass_off);
+        a.gpass = G.gpass.empty() ? nullptr : reinterpret_cast<const PassArgs *>(ws + G.desc + G.gpass_off);
         a.seg = reinterpret_cast<const ManySeg *>(ws + G.desc + G.seg_off);
         a.slot_out = reinterpret_cast<const uint16_t *>(ws + G.desc + G.slot_off);
         a.nseg = (int)G.seg.size();
@@ -2320,11 +2433,12 @@ static qq_status evaluate_many_impl(int count, qq_problem *const *problems, cons
             QQ_HIP(hipEventRecord(rec.start, stream));
         }
         int grid = 0;
-        QQ_HIP(launch_many(a, G.diag_type, opt ? opt->max_workgroups : 0, stream, &grid));
+        QQ_HIP(launch_many(a, c128, G.diag_type, opt ? opt->max_workgroups : 0, stream, &grid));
         if (g_prof) {
             QQ_HIP(hipEventRecord(rec.stop, stream));
             rec.meta.kind = 4;
             rec.meta.pass_kind = -1;
+            rec.meta.c128 = c128;
             rec.meta.diag_bytes = diag_bytes_of(G.diag_type);
             rec.meta.n = 0;
             rec.meta.batch = G.nstates;
@@ -2404,6 +2518,7 @@ static qq_status evaluate_many_guarded_impl(int count, qq_problem *const *proble
     if (qq_status st = validate_many(count, problems, p, batch, flags); st != QQ_OK) return st;
     if (flags & (QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE))
         return fail(QQ_E_UNSUPPORTED, "qq_evaluate_many_guarded takes host parameters and outputs");
+    if (flags & QQ_C128) return fail(QQ_E_UNSUPPORTED, "qq_evaluate_many_guarded evaluates in complex64 first");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(QQ_E_INVALID, "tol must be finite and >= 0");
     if (tol == 0.0) tol = 1e-5;
     const bool grad = flags & QQ_GRAD;

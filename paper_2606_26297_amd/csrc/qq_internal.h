@@ -204,13 +204,14 @@ struct ManyInst {
     const double *params;   // device [B][2p]
     const void *diag;
     const double *regq;     // device [n - 3][16]: register-run coupling sums (see qq_problem::regq)
-    void *psi, *lam;        // device [B][2^n] complex64 (multi-pass problems)
+    void *psi, *lam;        // device [B][2^n] complex64 (multi-pass problems), complex128 (every problem)
     double *energy_out;     // device [B], or NULL: results go to out_ws
     double *grad_out;       // device [B][2p] (with energy_out)
     double *out_ws;         // device [B][1 + 2p]
 };
 struct ManyPass {
     int kind, k, geom;      // geom 0: qubits 0..11; 1: high set, all 8 bits active; 2: high set, partial
+                            // (complex128 launch: kind -1, geom = states the general pass keeps, 1 or 2)
     int pos4, pos8, w1, w2, active, nact, store_psi;
     int slot_base, nslots;  // first accumulator slot of the pass inside its problem
     const double *ctab;     // the cost table of the pass's layout and its per-thread constants
@@ -223,6 +224,7 @@ struct ManySeg {
 struct ManyArgs {
     const ManyInst *inst;
     const ManyPass *pass;
+    const PassArgs *gpass;  // complex128 launch: the general pass of each ManyPass (same index), else NULL
     const ManySeg *seg;
     const uint16_t *slot_out;
     int nseg;
@@ -232,7 +234,7 @@ struct ManyArgs {
     double *partial;
     uint64_t spin_ticks;  // bound on one dependency wait, in wall-clock ticks
 };
-hipError_t launch_many(const ManyArgs &a, int diag_type, int max_grid, hipStream_t s, int *grid_out);
+hipError_t launch_many(const ManyArgs &a, bool c128, int diag_type, int max_grid, hipStream_t s, int *grid_out);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 
 // Device Adam step (qq_optim.hip).

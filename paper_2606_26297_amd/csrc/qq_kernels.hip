@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "qq_device.h"
+#include "qq_generic.h"
 
 namespace qq {
 namespace {
@@ -27,237 +28,17 @@ using namespace dev;
 template <typename R, int NS, typename DT>
 __global__ void __launch_bounds__(kThreads) pass_kernel(const PassArgs a)
 {
-    using C2 = typename Cx<R>::T;
-    using W = typename std::conditional<sizeof(R) == 4, float2, double>::type;
-    __shared__ W lds[kLdsSlots];
-    __shared__ R s_cb[QQ_MAX_P], s_sb[QQ_MAX_P];
-    __shared__ double s_gam[QQ_MAX_P];
-    __shared__ double s_red[kThreads / 64][kMaxLocalSlots];
-    __shared__ double s_imm[kMaxImmSlots];
-    __shared__ double s_wsum[kThreads / 64];
-
+    __shared__ gen::GenShared<R> sh;
     const int t = threadIdx.x;
-    for (int k = t; k < kMaxImmSlots; k += kThreads) s_imm[k] = 0.0;
     int b, g;
     block_coords(a.B, a.G, b, g);
-    {
-        const double *x = a.params + (size_t)b * 2 * a.p;
-        if (t < a.p) {
-            double sb, cb;
-            sincos(x[2 * t + 1], &sb, &cb);
-            s_cb[t] = (R)cb;
-            s_sb[t] = (R)sb;
-            s_gam[t] = x[2 * t];
-        }
-    }
-    __syncthreads();
-
-    const uint64_t off2 = (uint64_t)(t & 15) | ((uint64_t)(t >> 4) << a.pos4);
-    const uint64_t st2 = 1ull << a.pos8;
-    const uint64_t off1 = (uint64_t)(t & 15) | ((uint64_t)(t >> 4) << a.pos8);
-    const uint64_t st1 = 1ull << a.pos4;
-
-    C2 *psi = static_cast<C2 *>(a.psi) + (size_t)b * a.state_stride;
-    C2 *lam = NS > 1 ? static_cast<C2 *>(a.lam) + (size_t)b * a.state_stride : nullptr;
-
-    C2 v[NS][kRegs];
+    gen::gen_setup<R>(sh, a.params + (size_t)b * 2 * a.p, a.p, t);
     double acc[kMaxLocalSlots] = {0.0, 0.0, 0.0, 0.0};
-
-    for (uint64_t tile = g; tile < a.tiles; tile += a.G) {
-        uint64_t base;
-        if (a.high) base = tile_base(tile, a.pos4, a.pos8, a.w1, a.w2);
-        else base = tile << kTileBits;
-
-        int live = 0;
-        if (a.flags & PF_INIT) {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) v[0][r] = mk<C2, R>((R)a.amp0, (R)0);
-            live |= 1;
-        }
-        if (a.flags & PF_LOAD_PSI) {
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) v[0][r] = psi[base + off2 + r * st2];
-            live |= 1;
-        }
-        if constexpr (NS > 1) {
-            if (a.flags & PF_LOAD_LAM) {
-#pragma unroll
-                for (int r = 0; r < kRegs; ++r) v[1][r] = lam[base + off2 + r * st2];
-                live |= 2;
-            }
-        }
-        int cur = 2;
-
-        auto to_layout = [&](int to) {
-            if (to == cur) return;
-            if (live & 1) transpose1<W>(lds, v[0], t, cur, to);
-            if constexpr (NS > 1)
-                if (live & 2) transpose1<W>(lds, v[1], t, cur, to);
-            cur = to;
-        };
-        auto coalesced = [&]() {
-            if (cur == 0) to_layout(1);
-        };
-        // Slots 0..3 accumulate in registers across tiles; higher slots (only in
-        // single-pass plans) are reduced over the workgroup at once into LDS.
-        auto accumulate = [&](int slot, double val) {
-            if (slot < kMaxLocalSlots) {
-                add_slot(acc, slot, val);
-                return;
-            }
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) val += __shfl_xor(val, d, 64);
-            if ((t & 63) == 0) s_wsum[t >> 6] = val;
-            __syncthreads();
-            if (t == 0) s_imm[slot] += (s_wsum[0] + s_wsum[1]) + (s_wsum[2] + s_wsum[3]);
-            __syncthreads();
-        };
-
-        for (int o = 0; o < a.nops; ++o) {
-            const Op op = a.ops[o];
-            if (op.kind == OP_MIX) {
-                const R cb = s_cb[op.layer];
-                const R sb = (op.flags & OPF_INVERSE) ? -s_sb[op.layer] : s_sb[op.layer];
-                int seq[3], ns = 0;
-                const int need = (((op.active & 0x00f) != 0) << 0) | (((op.active & 0x0f0) != 0) << 1) |
-                                 (((op.active & 0xf00) != 0) << 2);
-                if (need & (1 << cur)) seq[ns++] = cur;
-                if ((need & 1) && cur != 0) seq[ns++] = 0;
-                if ((need & 2) && cur != 1) seq[ns++] = 1;
-                if ((need & 4) && cur != 2) seq[ns++] = 2;
-                for (int k = 0; k < ns; ++k) {
-                    const int gi = seq[k];
-                    to_layout(gi);
-                    const int m = (op.active >> (4 * gi)) & 15;
-                    double gacc = 0.0;
-#define QQ_BIT(K)                                                                   \
-    if (m & (1 << K)) {                                                             \
-        if constexpr (NS > 1)                                                       \
-            if (op.slot != kNoSlot) gacc += xexp_bit<K>(v[0], v[1]);                      \
-        if (op.states & 1) rx_bit<K>(v[0], cb, sb);                                 \
-        if constexpr (NS > 1)                                                       \
-            if (op.states & 2) rx_bit<K>(v[1], cb, sb);                             \
-    }
-                    QQ_BIT(0)
-                    QQ_BIT(1)
-                    QQ_BIT(2)
-                    QQ_BIT(3)
-#undef QQ_BIT
-                    if (op.slot != kNoSlot) accumulate(op.slot, gacc);
-                }
-            } else {
-                coalesced();
-                const uint64_t off = cur == 2 ? off2 : off1;
-                const uint64_t st = cur == 2 ? st2 : st1;
-                const double gam = s_gam[op.layer];
-                double tacc = 0.0;
-                if (op.kind == OP_PHASE) {
-                    const bool inv = op.flags & OPF_INVERSE;
-#pragma unroll
-                    for (int r = 0; r < kRegs; ++r) {
-                        const uint64_t gi = (base + off + r * st) & a.dim_mask;
-                        if (op.flags & OPF_PARTITIONED) {
-                            for (int m = 0; m < a.part->nparts + 1; ++m) {
-                                double cm;
-                                if (m < a.part->nparts)
-                                    cm = ldc<DT>(a.part_tables, a.part->table_off[m] +
-                                                                    compress_bits(gi, a.part->vars[m], a.part->nvars[m]));
-                                else cm = ldc<DT>(a.cross_diag, gi);
-                                R c, s;
-                                phase_cs(gam * cm, c, s);
-                                if (inv) s = -s;
-                                if (op.states & 1) rot_phase<R>(v[0][r], c, s);
-                                if constexpr (NS > 1)
-                                    if (op.states & 2) rot_phase<R>(v[1][r], c, s);
-                            }
-                        } else {
-                            R c, s;
-                            phase_cs(gam * ldc<DT>(a.diag, gi), c, s);
-                            if (inv) s = -s;
-                            if (op.states & 1) rot_phase<R>(v[0][r], c, s);
-                            if constexpr (NS > 1)
-                                if (op.states & 2) rot_phase<R>(v[1][r], c, s);
-                        }
-                    }
-                } else if (op.kind == OP_ENERGY || op.kind == OP_ENERGY_LAMBDA) {
-#pragma unroll
-                    for (int r = 0; r < kRegs; ++r) {
-                        const uint64_t gi = (base + off + r * st) & a.dim_mask;
-                        const double cz = ldc<DT>(a.diag, gi);
-                        const double re = (double)v[0][r].x, im = (double)v[0][r].y;
-                        tacc = fma(fma(re, re, im * im), cz, tacc);
-                        if constexpr (NS > 1)
-                            if (op.kind == OP_ENERGY_LAMBDA) v[1][r] = mk<C2, R>((R)(cz * re), (R)(cz * im));
-                    }
-                    if (op.kind == OP_ENERGY_LAMBDA) live |= 2;
-                } else if (op.kind == OP_GGAMMA) {
-                    if constexpr (NS > 1) {
-                        const bool unph = op.flags & OPF_UNPHASE;
-#pragma unroll
-                        for (int r = 0; r < kRegs; ++r) {
-                            const uint64_t gi = (base + off + r * st) & a.dim_mask;
-                            const double cz = ldc<DT>(a.diag, gi);
-                            const C2 ps = v[0][r], la = v[1][r];
-                            const double im = fma((double)la.x, (double)ps.y, -(double)la.y * (double)ps.x);
-                            tacc = fma(cz, im, tacc);
-                            if (unph) {
-                                if (op.flags & OPF_PARTITIONED) {
-                                    for (int m = 0; m < a.part->nparts + 1; ++m) {
-                                        double cm;
-                                        if (m < a.part->nparts)
-                                            cm = ldc<DT>(a.part_tables,
-                                                         a.part->table_off[m] +
-                                                             compress_bits(gi, a.part->vars[m], a.part->nvars[m]));
-                                        else cm = ldc<DT>(a.cross_diag, gi);
-                                        R c, s;
-                                        phase_cs(gam * cm, c, s);
-                                        rot_phase<R>(v[0][r], c, -s);
-                                        rot_phase<R>(v[1][r], c, -s);
-                                    }
-                                } else {
-                                    R c, s;
-                                    phase_cs(gam * cz, c, s);
-                                    rot_phase<R>(v[0][r], c, -s);
-                                    rot_phase<R>(v[1][r], c, -s);
-                                }
-                            }
-                        }
-                    }
-                }
-                if (op.slot != kNoSlot) accumulate(op.slot, tacc);
-            }
-        }
-
-        if (a.flags & (PF_STORE_PSI | PF_STORE_LAM)) {
-            coalesced();
-            const uint64_t off = cur == 2 ? off2 : off1;
-            const uint64_t st = cur == 2 ? st2 : st1;
-#pragma unroll
-            for (int r = 0; r < kRegs; ++r) {
-                const uint64_t gi = base + off + r * st;
-                if (gi & ~a.dim_mask) continue;  // replicated copies of a state smaller than a tile
-                if (a.flags & PF_STORE_PSI) psi[gi] = v[0][r];
-                if constexpr (NS > 1)
-                    if (a.flags & PF_STORE_LAM) lam[gi] = v[1][r];
-            }
-        }
-    }
-
-    // Fixed-order workgroup reduction of the FP64 accumulators.
-    const int lane = t & 63, wave = t >> 6;
-#pragma unroll
-    for (int s = 0; s < kMaxLocalSlots; ++s) {
-        if (s >= a.nslots) break;
-        double x = acc[s];
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-        if (lane == 0) s_red[wave][s] = x;
-    }
-    __syncthreads();
-    for (int s = t; s < a.nslots; s += kThreads) {
-        const double sum = s < kMaxLocalSlots ? ((s_red[0][s] + s_red[1][s]) + (s_red[2][s] + s_red[3][s])) : s_imm[s];
+    gen::gen_tiles<R, NS, DT>(a, sh, t, b, (uint64_t)g, a.tiles, (uint64_t)a.G, acc);
+    // fixed-order workgroup reduction of the FP64 accumulators
+    gen::gen_slot_totals<R>(a.nslots, acc, sh, t, [&](int s, double sum) __attribute__((always_inline)) {
         a.partial[(size_t)(a.slot_base + s) * a.slot_stride + (size_t)b * a.G + g] = sum;
-    }
+    });
 }
 
 // out[b][o] = scale_o * sum over the slots mapped to o of sum_g partial[slot][b][g].

@@ -6,6 +6,9 @@
 // on a state once every chunk of pass j on that state has completed.  A problem
 // with n <= 12 is a single item: one workgroup runs the whole evaluation (all p
 // layers, the energy and the adjoint sweep) on one register-resident tile.
+// The complex128 launch (many128_kernel) runs the general pass bodies on
+// complex128 states instead, one chunk of tiles per item for every problem
+// (a problem with n <= 12 has one pass of one tile).
 //
 // Ordering and progress.  Tickets are handed out in increasing order from one
 // atomic counter, and items are numbered level-major (pass 0 of every problem,
@@ -26,6 +29,7 @@
 // its own; the workgroup that completes the last item of a state sums the
 // partials in a fixed order (slots ascending, chunks ascending), so results are
 // reproducible run to run.
+#include "qq_generic.h"
 #include "qq_passes.h"
 
 namespace qq {
@@ -293,14 +297,13 @@ __device__ void finish_state(const ManyArgs &A, const ManyInst &I, int b, int t)
     }
 }
 
-template <typename DT>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) many_kernel(const ManyArgs A)
+// The queue of a persistent launch: take tickets until every item is taken or an error is flagged;
+// wait until the item's state has completed its earlier passes, run(I, pass, b, chunk), publish
+// the item, and let the workgroup that completes a state's last item finish that state.  The item
+// bodies are lambdas marked always_inline: called out of line, they spill registers across the call.
+template <typename Run>
+__device__ __forceinline__ void drain_queue(const ManyArgs &A, uint32_t *s_msg, int t, Run run)
 {
-    __shared__ float2 lds[kLdsSlots];
-    __shared__ double s_red[kThreads / 64];
-    __shared__ uint32_t s_msg[2];
-    __shared__ MixCoef s_coef[2 * QQ_MAX_P];
-    const int t = threadIdx.x;
     uint32_t *head = A.ctl, *err = A.ctl + 1, *cnt = A.ctl + 2;
 
     for (;;) {
@@ -358,18 +361,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
             if (!ok) break;
         }
 
-        const ManyPass &P = A.pass[I.pass_off + (int)sg.pass];
-        // The thread index, opaque per item: keeps each body's index arithmetic
-        // inside its own branch instead of hoisted out of the item loop (where
-        // the values of every body would stay live at once).
-        int ti = t;
-        asm volatile("" : "+v"(ti));
-        if (P.kind == FK_SINGLE) {
-            if (A.grad) single_eval<DT, true>(I, A.partial, lds, s_red, s_coef, ti, b);
-            else single_eval<DT, false>(I, A.partial, lds, s_red, s_coef, ti, b);
-        } else {
-            run_chunk<DT>(I, P, A.partial, lds, s_red, ti, b, chunk);
-        }
+        run(I, (int)sg.pass, b, chunk);
 
         // publish: every wave waits for its own stores to complete (to the XCD's L2), the
         // barrier orders them before thread 0, whose agent-scope release writes the L2
@@ -387,36 +379,90 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
     }
 }
 
+template <typename DT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) many_kernel(const ManyArgs A)
+{
+    __shared__ float2 lds[kLdsSlots];
+    __shared__ double s_red[kThreads / 64];
+    __shared__ uint32_t s_msg[2];
+    __shared__ MixCoef s_coef[2 * QQ_MAX_P];
+    const int t = threadIdx.x;
+    drain_queue(A, s_msg, t, [&](const ManyInst &I, int pass, int b, int chunk) __attribute__((always_inline)) {
+        const ManyPass &P = A.pass[I.pass_off + pass];
+        // The thread index, opaque per item: keeps each body's index arithmetic
+        // inside its own branch instead of hoisted out of the item loop (where
+        // the values of every body would stay live at once).
+        int ti = t;
+        asm volatile("" : "+v"(ti));
+        if (P.kind == FK_SINGLE) {
+            if (A.grad) single_eval<DT, true>(I, A.partial, lds, s_red, s_coef, ti, b);
+            else single_eval<DT, false>(I, A.partial, lds, s_red, s_coef, ti, b);
+        } else {
+            run_chunk<DT>(I, P, A.partial, lds, s_red, ti, b, chunk);
+        }
+    });
+}
+
+// Complex128 states: the general pass body of item (problem, parameter set b, pass, chunk) over the
+// chunk's consecutive tiles, its slot totals into the item's partial sums.
+template <typename DT>
+__global__ void __launch_bounds__(kThreads) many128_kernel(const ManyArgs A)
+{
+    __shared__ gen::GenShared<double> sh;
+    __shared__ uint32_t s_msg[2];
+    const int t = threadIdx.x;
+    drain_queue(A, s_msg, t, [&](const ManyInst &I, int pass, int b, int chunk) __attribute__((always_inline)) {
+        const ManyPass &P = A.pass[I.pass_off + pass];
+        const PassArgs &a = A.gpass[I.pass_off + pass];
+        gen::gen_setup<double>(sh, I.params + (size_t)b * 2 * I.p, I.p, t);
+        double acc[kMaxLocalSlots] = {0.0, 0.0, 0.0, 0.0};
+        const uint64_t t0 = (uint64_t)chunk * (uint64_t)I.tpc, t1 = min(I.tiles, t0 + (uint64_t)I.tpc);
+        if (P.geom > 1) gen::gen_tiles<double, 2, DT>(a, sh, t, b, t0, t1, 1, acc);
+        else gen::gen_tiles<double, 1, DT>(a, sh, t, b, t0, t1, 1, acc);
+        gen::gen_slot_totals<double>(P.nslots, acc, sh, t, [&](int s, double sum) __attribute__((always_inline)) {
+            A.partial[I.partial_off + ((size_t)(P.slot_base + s) * I.B + b) * I.nchunks + chunk] = sum;
+        });
+    });
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-template <typename DT>
-hipError_t launch_many_t(const ManyArgs &a, int max_grid, hipStream_t s, int *grid_out)
+// As many workgroups as can be resident at once (every one of them then runs until the queue is
+// drained), at most max_grid (> 0) and at most one per item.
+template <typename K>
+hipError_t launch_resident(K kernel, const ManyArgs &a, int max_grid, hipStream_t s, int *grid_out)
 {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, many_kernel<DT>, kThreads, 0)) != hipSuccess)
-        return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0)) != hipSuccess) return e;
     long grid = (long)std::max(1, per_cu) * std::max(1, cus);
     if (max_grid > 0) grid = std::min<long>(grid, max_grid);
     grid = std::max(1L, std::min<long>(grid, (long)a.total));
     if (grid_out) *grid_out = (int)grid;
-    hipLaunchKernelGGL(many_kernel<DT>, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
     return hipGetLastError();
+}
+
+template <typename DT>
+hipError_t launch_many_t(const ManyArgs &a, bool c128, int max_grid, hipStream_t s, int *grid_out)
+{
+    return c128 ? launch_resident(many128_kernel<DT>, a, max_grid, s, grid_out)
+                : launch_resident(many_kernel<DT>, a, max_grid, s, grid_out);
 }
 
 }  // namespace
 
-hipError_t launch_many(const ManyArgs &a, int diag_type, int max_grid, hipStream_t s, int *grid_out)
+hipError_t launch_many(const ManyArgs &a, bool c128, int diag_type, int max_grid, hipStream_t s, int *grid_out)
 {
     switch (diag_type) {
-    case DIAG_F64: return launch_many_t<double>(a, max_grid, s, grid_out);
-    case DIAG_I32: return launch_many_t<int32_t>(a, max_grid, s, grid_out);
-    default: return launch_many_t<int16_t>(a, max_grid, s, grid_out);
+    case DIAG_F64: return launch_many_t<double>(a, c128, max_grid, s, grid_out);
+    case DIAG_I32: return launch_many_t<int32_t>(a, c128, max_grid, s, grid_out);
+    default: return launch_many_t<int16_t>(a, c128, max_grid, s, grid_out);
     }
 }
 

@@ -699,7 +699,7 @@ def kernel_name(rec) -> str:
     if rec["kind"] == 3:
         return "finalize_kernel"
     if rec["kind"] == 4:
-        return f"many_kernel<{DIAG_TYPE_NAMES[rec['diag_bytes']]}>"
+        return f"{'many128_kernel' if rec['c128'] else 'many_kernel'}<{DIAG_TYPE_NAMES[rec['diag_bytes']]}>"
     if rec["kind"] in AUX_KIND_NAMES:
         return AUX_KIND_NAMES[rec["kind"]]
     dt = DIAG_TYPE_NAMES[rec["diag_bytes"]]

@@ -141,16 +141,17 @@ class Problem:
         return N.qq_evaluate_plain(self.handle, x.shape[0] // 2, x, N.QQ_GRAD if grad else N.QQ_ENERGY)
 
 
-def evaluate_many(problems, params, grad=False, options=None, workspace=None):
+def evaluate_many(problems, params, grad=False, options=None, workspace=None, c128=False):
     """Energies (and gradients) of many problems in one persistent launch per diagonal type.
 
     problems: list of Problem; params: list of [B_i, 2p_i] arrays (numpy: host path) or
     CUDA tensors (device path).  options: dict with tiles_per_chunk, max_workgroups,
-    wait_limit_ms (0 = automatic).  Returns (energies, grads) as lists (grads None without grad).
+    wait_limit_ms (0 = automatic).  c128: complex128 states.  Returns (energies, grads) as
+    lists (grads None without grad).
     """
     import torch
 
-    flags = N.QQ_ENERGY | (N.QQ_GRAD if grad else 0)
+    flags = N.QQ_ENERGY | (N.QQ_GRAD if grad else 0) | (N.QQ_C128 if c128 else 0)
     handles = [pb.handle for pb in problems]
     dev = len(params) > 0 and isinstance(params[0], torch.Tensor) and params[0].is_cuda
     if dev:

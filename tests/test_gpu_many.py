@@ -7,7 +7,8 @@ Tolerances: 1e-5 relative against the oracle (energy |dE| / max(|E|, sigma_C),
 gradient ||dg||_inf / ||g||_inf); 1e-9 relative against qq_evaluate for n >= 13
 (same complex64 arithmetic per amplitude, only the order of the FP64 partial sums
 differs) and 1e-5 for n <= 12 (a different single-tile kernel); bit-identical
-results across grid sizes (fixed-order reductions).
+results across grid sizes (fixed-order reductions).  Complex128 states (QQ_C128):
+1e-10 against the oracle, 1e-11 against per-problem complex128 calls.
 """
 import numpy as np
 import pytest
@@ -103,6 +104,42 @@ def test_many_vs_oracle_and_per_problem(mix):
             assert g_err(g[k][b], gr) <= 1e-5, (k, b)
 
 
+def test_many_c128_vs_per_problem_and_oracle(mix):
+    """The complex128 launch runs the general pass bodies of the per-pass complex128 kernels: same
+    arithmetic per amplitude, only the set order and the order of the FP64 partial sums differ, so
+    1e-11 against per-problem complex128 calls; 1e-10 against the oracle (n <= 17)."""
+    insts, pbs = mix
+    xs = [x for _, x in insts]
+    e, g = evaluate_many(pbs, xs, grad=True, c128=True)
+    e0, g0 = evaluate_many(pbs, xs, grad=False, c128=True)
+    assert g0 is None
+    for k, ((inst, x), pb) in enumerate(zip(insts, pbs)):
+        sig = pb.info.sigma_c
+        print(f"problem {k}: n={pb.n} p={x.shape[1] // 2} B={x.shape[0]}", flush=True)
+        e1, g1 = pb.evaluate(x, grad=True, c128=True)
+        assert e_err(e[k], e1, sig) <= 1e-11, (k, e[k], e1)
+        assert g_err(g[k], g1) <= 1e-11, k
+        assert e_err(e0[k], e1, sig) <= 1e-11, k
+        if pb.n <= 17:
+            d = O.cost_diagonal(inst.H, inst.f, inst.c0)
+            for b in range(x.shape[0]):
+                er, gr = O.gradient(d, x[b])
+                assert e_err(e[k][b], er, sig) <= 1e-10, (k, b)
+                assert g_err(g[k][b], gr) <= 1e-10, (k, b)
+
+
+def test_many_c128_bitwise_across_grids_and_close_across_chunks(mix):
+    insts, pbs = mix
+    xs = [x for _, x in insts]
+    ea, ga = evaluate_many(pbs, xs, grad=True, c128=True)
+    eb, gb = evaluate_many(pbs, xs, grad=True, c128=True, options={"max_workgroups": 5})
+    ec, gc = evaluate_many(pbs, xs, grad=True, c128=True, options={"tiles_per_chunk": 1})
+    for k, pb in enumerate(pbs):
+        assert np.array_equal(ea[k], eb[k]) and np.array_equal(ga[k], gb[k]), k
+        assert e_err(ec[k], ea[k], pb.info.sigma_c) <= 1e-12, k
+        assert g_err(gc[k], ga[k]) <= 1e-12, k
+
+
 def test_many_energy_only_matches_grad_run(mix):
     insts, pbs = mix
     xs = [x for _, x in insts]
@@ -153,7 +190,7 @@ def test_many_rejects_unsupported_and_bad_arguments(mix):
     e = [np.empty(1)]
     g = [np.empty((1, 2))]
     with pytest.raises(N.QQError) as ei:
-        N.qq_evaluate_many([pbs[0].handle], [1], [1], x, N.QQ_ENERGY | N.QQ_C128, None, None, 0, None, e, g)
+        N.qq_evaluate_many([pbs[0].handle], [1], [1], x, N.QQ_ENERGY | N.QQ_PARTITIONED, None, None, 0, None, e, g)
     assert ei.value.status == N.QQ_E_UNSUPPORTED
     with pytest.raises(N.QQError) as ei:
         N.qq_evaluate_many([pbs[0].handle], [1], [0], x, N.QQ_ENERGY, None, None, 0, None, e, g)
