@@ -239,10 +239,46 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def uneven_batch(dev, reps=5, pinned=None, persistent_only=False):
+def guarded_leg(items, pbs, opt, ref):
+    """The guarded evaluation of the uneven batch (host inputs and outputs): complex64 persistent launch, then
+    complex128 for the sets whose stated complex64 gradient bound exceeds 1e-5 of the gradient."""
+    import numpy as np
+
+    import torch
+
+    from paper_2606_26297_amd import native as N
+    from paper_2606_26297_amd.qaoa import evaluate_many_guarded
+
+    xs_h = [x for _, x in items]
+    evaluate_many_guarded(pbs, xs_h, tol=1e-5, options=opt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eg, gg, up, errb = evaluate_many_guarded(pbs, xs_h, tol=1e-5, options=opt)
+    t_guard = time.perf_counter() - t0
+    gq = [float(np.max(np.abs(gg[k][0] - np.array(ref[k]["gradient"]))) / np.max(np.abs(ref[k]["gradient"])))
+          for k in range(len(items))]
+    guarded = {"ms": round(1000 * t_guard, 2), "sets_in_complex128": int(sum(int(u[0]) for u in up)),
+               "grad_rel_max": max(gq), "grad_rel_over_1e-5": int(sum(v > 1e-5 for v in gq)),
+               "bound_holds": bool(all(gq[k] * np.max(np.abs(ref[k]["gradient"])) <= errb[k][0]
+                                       for k in range(len(items)))),
+               "note": "host inputs and outputs, workspaces allocated by the library; the flagged sets are "
+                       "recomputed by one persistent complex128 launch (qq_evaluate_many with QQ_C128)"}
+    # the two launches of a second guarded call, timed with HIP events
+    N.qq_profile_enable(True)
+    N.qq_profile_read()
+    evaluate_many_guarded(pbs, xs_h, tol=1e-5, options=opt)
+    N.qq_profile_enable(False)
+    recs = [r for r in N.qq_profile_read() if r["kind"] == 4]
+    guarded["kernel_ms"] = {N.kernel_name(r): round(r["ms"], 3) for r in recs}
+    guarded["kernel_algorithmic_GBps"] = {N.kernel_name(r): round(r["bytes"] / (r["ms"] / 1000.0) / 1e9, 1)
+                                          for r in recs}
+    return guarded
+
+
+def uneven_batch(dev, reps=5, pinned=None, persistent_only=False, guarded_only=False):
     """The 512-problem uneven batch: persistent launch vs per-problem launches (device-resident).
     pinned: persistent-launch options to use instead of autotuning them; persistent_only: skip the
-    per-problem launches (about 26 000 dispatches)."""
+    per-problem launches (about 26 000 dispatches); guarded_only: only the guarded evaluation."""
     import numpy as np
     import torch
 
@@ -260,6 +296,9 @@ def uneven_batch(dev, reps=5, pinned=None, persistent_only=False):
     es = [torch.empty(b, dtype=torch.float64, device=dev) for b in bs]
     gs = [torch.empty(x.shape, dtype=torch.float64, device=dev) for x in xs]
     stream = torch.cuda.current_stream(dev)
+    if guarded_only:
+        return {"workload": "512 dense integer QUBOs, n ~ U{10..22}, p ~ U{1..6}, 1 parameter set each, energy+grad",
+                "guarded": guarded_leg(items, pbs, pinned, load_golden("uneven512_oracle.json")["problems"])}
     if pinned is None:
         opt, tune_ms = N.qq_autotune_many(handles, ps, bs, flags, None, stream)
     else:
@@ -320,30 +359,7 @@ def uneven_batch(dev, reps=5, pinned=None, persistent_only=False):
         dg = float(np.max(np.abs(g_many[k][0].cpu().numpy() - gr)))
         g_rel.append(dg / float(np.max(np.abs(gr))))
         g_abs.append(dg / sig[k])
-    # the guarded evaluation of the same batch (host inputs and outputs): complex64 persistent launch, then
-    # complex128 for the sets whose stated complex64 gradient bound exceeds 1e-5 of the gradient
-    from paper_2606_26297_amd.qaoa import evaluate_many_guarded
-
-    xs_h = [x for _, x in items]
-    evaluate_many_guarded(pbs, xs_h, tol=1e-5, options=opt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    eg, gg, up, errb = evaluate_many_guarded(pbs, xs_h, tol=1e-5, options=opt)
-    t_guard = time.perf_counter() - t0
-    gq = [float(np.max(np.abs(gg[k][0] - np.array(ref[k]["gradient"]))) / np.max(np.abs(ref[k]["gradient"])))
-          for k in range(len(items))]
-    guarded = {"ms": round(1000 * t_guard, 2), "sets_in_complex128": int(sum(int(u[0]) for u in up)),
-               "grad_rel_max": max(gq), "grad_rel_over_1e-5": int(sum(v > 1e-5 for v in gq)),
-               "bound_holds": bool(all(gq[k] * np.max(np.abs(ref[k]["gradient"])) <= errb[k][0]
-                                       for k in range(len(items)))),
-               "note": "host inputs and outputs, workspaces allocated by the library; the flagged sets are "
-                       "recomputed by one persistent complex128 launch (qq_evaluate_many with QQ_C128)"}
-    # the two launches of a second guarded call, timed with HIP events
-    N.qq_profile_enable(True)
-    N.qq_profile_read()
-    evaluate_many_guarded(pbs, xs_h, tol=1e-5, options=opt)
-    N.qq_profile_enable(False)
-    guarded["kernel_ms"] = {N.kernel_name(r): round(r["ms"], 3) for r in N.qq_profile_read() if r["kind"] == 4}
+    guarded = guarded_leg(items, pbs, opt, ref)
     vs_oracle = {"problems": len(items), "energy_rel_max": max(e_rel), "grad_rel_max": max(g_rel),
                  "grad_rel_median": float(np.median(g_rel)), "grad_rel_over_1e-5": int(sum(v > 1e-5 for v in g_rel)),
                  "grad_abs_over_sigma_max": max(g_abs),
@@ -786,6 +802,8 @@ def main():
     ap.add_argument("--schedule", default=None, metavar="G:PAIRING[:ORDER[:SETORDER]]",
                     help="pin this schedule (workgroups per state, set pairing, tile order, set order) "
                          "instead of autotuning")
+    ap.add_argument("--guarded-only", action="store_true",
+                    help="with --uneven-only: only the guarded evaluation (complex64 launch, complex128 recomputation)")
     ap.add_argument("--persistent-only", action="store_true",
                     help="with --uneven-only: time only the persistent launch (no per-problem launches)")
     ap.add_argument("--aux-only", action="store_true",
@@ -838,7 +856,8 @@ def main():
         pinned_many = {"tiles_per_chunk": tpc, "max_workgroups": cap, "wait_limit_ms": 0.0}
     if args.uneven_only:
         progress("uneven batch")
-        res = {"uneven_batch": uneven_batch(dev, pinned=pinned_many, persistent_only=args.persistent_only)}
+        res = {"uneven_batch": uneven_batch(dev, pinned=pinned_many, persistent_only=args.persistent_only,
+                                            guarded_only=args.guarded_only)}
         if args.copy_calibration:
             res["copy_calibration"] = copy_calibration(dev)
         print(json.dumps(res), flush=True)

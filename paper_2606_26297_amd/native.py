@@ -215,25 +215,68 @@ def _need(p, batch, per):
     return batch * per(p) * 8 if 1 <= p <= QQ_MAX_P and batch >= 1 else 0
 
 
+_DT_NAMES = {}
+
+
+def _np_dtype_name(dt):
+    """numpy's element-type name, cached per dtype (dtype.name costs microseconds per call, which
+    adds up over the per-problem buffers of a many-problem call)."""
+    name = _DT_NAMES.get(dt)
+    if name is None:
+        name = _DT_NAMES[dt] = dt.name
+    return name
+
+
+def _host_addr(x, nbytes, name, dtypes, index=None):
+    """Address of a C-contiguous numpy array of an accepted element type holding at least nbytes
+    (name, or name[index], in the error messages)."""
+    if not isinstance(x, np.ndarray) or not x.flags.c_contiguous:
+        raise ValueError(f"{_label(name, index)}: a C-contiguous numpy array is required")
+    dt = _np_dtype_name(x.dtype)
+    if dtypes is not None and dt not in dtypes:
+        raise TypeError(f"{_label(name, index)}: element type {dt}, expected one of {', '.join(dtypes)}")
+    if x.nbytes < nbytes:
+        raise ValueError(f"{_label(name, index)}: holds {x.nbytes} bytes, {nbytes} needed")
+    return x.__array_interface__["data"][0]
+
+
+def _label(name, index):
+    return name if index is None else f"{name}[{index}]"
+
+
 def _buf(x, nbytes, name, device, dtypes=None):
     """Address of a caller buffer after checking it: a contiguous CUDA tensor (device) or a
     C-contiguous numpy array (host) of an accepted element type holding at least nbytes.  A short or
     strided buffer would otherwise be read or written out of bounds by the library."""
-    if device:
-        if not getattr(x, "is_cuda", False):
-            raise ValueError(f"{name}: a CUDA tensor is required with the *_ON_DEVICE flag")
-        if not x.is_contiguous():
-            raise ValueError(f"{name}: the tensor must be contiguous")
-        size, dt, addr = x.numel() * x.element_size(), str(x.dtype).replace("torch.", ""), int(x.data_ptr())
-    else:
-        if not isinstance(x, np.ndarray) or not x.flags["C_CONTIGUOUS"]:
-            raise ValueError(f"{name}: a C-contiguous numpy array is required")
-        size, dt, addr = x.nbytes, x.dtype.name, x.ctypes.data
+    if not device:
+        return ctypes.c_void_p(_host_addr(x, nbytes, name, dtypes))
+    if not getattr(x, "is_cuda", False):
+        raise ValueError(f"{name}: a CUDA tensor is required with the *_ON_DEVICE flag")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: the tensor must be contiguous")
+    size, dt, addr = x.numel() * x.element_size(), str(x.dtype).replace("torch.", ""), int(x.data_ptr())
     if dtypes is not None and dt not in dtypes:
         raise TypeError(f"{name}: element type {dt}, expected one of {', '.join(dtypes)}")
     if size < nbytes:
         raise ValueError(f"{name}: holds {size} bytes, {nbytes} needed")
     return ctypes.c_void_p(addr)
+
+
+def _bufs(xs, sizes, name, device, dtypes=None):
+    """ctypes array of the addresses of one buffer per problem, each checked as _buf checks one."""
+    sizes = [int(v) for v in sizes]
+    if device:
+        addrs = [_buf(x, sizes[i], f"{name}[{i}]", True, dtypes).value for i, x in enumerate(xs)]
+    else:
+        addrs = [_host_addr(x, sizes[i], name, dtypes, i) for i, x in enumerate(xs)]
+    return (_vp * len(addrs))(*addrs)
+
+
+def _need_many(pa, ba, doubles_per_p, doubles_fixed=0):
+    """Bytes of each problem's buffer of (doubles_per_p * p + doubles_fixed) doubles per parameter set,
+    0 where p or batch is out of range (the library then rejects the call with its own error code)."""
+    ok = (pa >= 1) & (pa <= QQ_MAX_P) & (ba >= 1)
+    return np.where(ok, ba.astype(np.int64) * (doubles_per_p * pa.astype(np.int64) + doubles_fixed) * 8, 0)
 
 
 # ---- one wrapper per entry point ------------------------------------------------------------
@@ -385,16 +428,13 @@ def qq_evaluate_many_guarded(handles, p, batch, params, flags, opt, tol, energy_
     count, hs, pa, ba = _many_arrays(handles, p, batch)
     if len(params) != count or len(energy_out) != count or (grad_out is not None and len(grad_out) != count):
         raise ValueError("params, energy_out and grad_out need one entry per problem")
-    sizes = [_need(pa[i], ba[i], lambda q: 2 * q) for i in range(count)]
-    ones = [_need(pa[i], ba[i], lambda q: 1) for i in range(count)]
-    pp = (_vp * count)(*[_buf(params[i], sizes[i], f"params[{i}]", False, _F64).value for i in range(count)])
-    ep = (_vp * count)(*[_buf(energy_out[i], ones[i], f"energy_out[{i}]", False, _F64).value for i in range(count)])
-    gp = None if grad_out is None else (_vp * count)(
-        *[_buf(grad_out[i], sizes[i], f"grad_out[{i}]", False, _F64).value for i in range(count)])
-    cp = None if c128_out is None else (_vp * count)(
-        *[_buf(c128_out[i], 4 * int(ba[i]), f"c128_out[{i}]", False, ("int32",)).value for i in range(count)])
-    rp = None if grad_err_out is None else (_vp * count)(
-        *[_buf(grad_err_out[i], ones[i], f"grad_err_out[{i}]", False, _F64).value for i in range(count)])
+    sizes, ones = _need_many(pa, ba, 2), _need_many(pa, ba, 0, 1)
+    pp = _bufs(params, sizes, "params", False, _F64)
+    ep = _bufs(energy_out, ones, "energy_out", False, _F64)
+    gp = None if grad_out is None else _bufs(grad_out, sizes, "grad_out", False, _F64)
+    cp = None if c128_out is None else _bufs(c128_out, 4 * np.maximum(ba.astype(np.int64), 0), "c128_out", False,
+                                             ("int32",))
+    rp = None if grad_err_out is None else _bufs(grad_err_out, ones, "grad_err_out", False, _F64)
     _check(lib().qq_evaluate_many_guarded(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
                                           ctypes.cast(pp, _vp), int(flags), _many_options(opt), float(tol),
                                           _stream_ptr(stream), ctypes.cast(ep, _vp),
@@ -437,12 +477,10 @@ def qq_evaluate_many(handles, p, batch, params, flags, opt, workspace, ws_bytes,
     pout = flags & QQ_OUT_ON_DEVICE
     if len(params) != count or len(energy_out) != count or (grad_out is not None and len(grad_out) != count):
         raise ValueError("params, energy_out and grad_out need one entry per problem")
-    sizes = [_need(pa[i], ba[i], lambda q: 2 * q) for i in range(count)]
-    pp = (_vp * count)(*[_buf(params[i], sizes[i], f"params[{i}]", pin, _F64).value for i in range(count)])
-    ep = (_vp * count)(*[_buf(energy_out[i], _need(pa[i], ba[i], lambda q: 1), f"energy_out[{i}]", pout, _F64).value
-                         for i in range(count)])
-    gp = (_vp * count)(*[_buf(grad_out[i], sizes[i], f"grad_out[{i}]", pout, _F64).value
-                         if grad_out is not None else None for i in range(count)])
+    sizes = _need_many(pa, ba, 2)
+    pp = _bufs(params, sizes, "params", pin, _F64)
+    ep = _bufs(energy_out, _need_many(pa, ba, 0, 1), "energy_out", pout, _F64)
+    gp = _bufs(grad_out, sizes, "grad_out", pout, _F64) if grad_out is not None else None
     wp = None if workspace is None else _buf(workspace, int(ws_bytes), "workspace", True)
     _check(lib().qq_evaluate_many(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
                                   ctypes.cast(pp, _vp), int(flags), _many_options(opt), wp, int(ws_bytes),
