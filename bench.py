@@ -825,7 +825,7 @@ def main():
                     help="skip the 12-variable and unit-commitment-shaped workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (reference kernel for the traffic counters) and "
-                         "report its rate")
+                         "report its rate in the --uneven-only / --aux-only legs (the full run always does)")
     args = ap.parse_args()
 
     if args.summarize_counters:
@@ -982,8 +982,8 @@ def main():
     del ws
     torch.cuda.empty_cache()
 
-    if args.copy_calibration:
-        out["copy_calibration"] = copy_calibration(dev)
+    # a plain device copy beside the kernels: the practical bandwidth reference of this GPU
+    out["copy_calibration"] = copy_calibration(dev)
     if not args.no_check:
         # sampled parity at full size: complex64 timed path vs the complex128 fused path (both GPU)
         e64 = e_out[:2].cpu().numpy()
