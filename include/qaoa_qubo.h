@@ -223,7 +223,7 @@ qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int 
  * QQ_E_NOMEM, QQ_E_DEVICE.
  */
 typedef struct {
-    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: 16 (QQ_C128: 4) */
+    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: 16 (QQ_C128: 8) */
     int max_workgroups;    /* cap on the persistent grid; 0: every workgroup that fits on the device at once */
     double wait_limit_ms;  /* bound on one dependency wait; 0: 2000 ms */
 } qq_many_options;

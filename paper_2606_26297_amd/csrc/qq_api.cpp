@@ -1094,9 +1094,10 @@ int many_tiles_per_chunk(uint64_t tiles, const qq_many_options *opt, bool c128)
     // cache write-back and two device-scope atomics, which a 16-tile item amortises,
     // while a 2^22-amplitude pass still splits into 64 items (measured on MI355X with
     // the 512-problem uneven batch: 1 tile 107 ms, 8 tiles 30 ms, 16 and 32 tiles 25 ms).
-    // Complex128 (one resident workgroup per compute unit): 4 tiles, so that the batch's
-    // longest chains split finely (its 88 flagged sets: 4 tiles 11.3 ms, 16 11.7, 64 25.5)
-    const uint64_t want = (opt && opt->tiles_per_chunk > 0) ? (uint64_t)opt->tiles_per_chunk : (c128 ? 4 : 16);
+    // Complex128 (one resident workgroup per compute unit): 8 tiles, so that the longest pass
+    // chains split finely (the batch's 88 flagged sets: 2 tiles 13.5 ms, 4 11.4, 8 10.6, 16 11.8,
+    // 64 25.5)
+    const uint64_t want = (opt && opt->tiles_per_chunk > 0) ? (uint64_t)opt->tiles_per_chunk : (c128 ? 8 : 16);
     return (int)std::min<uint64_t>(want, tiles);
 }
 
