@@ -27,7 +27,7 @@ struct GenShared {
     double wsum[kThreads / 64];
 };
 
-// Layer constants of the parameter set x (2p values, gamma_k then beta_k) and cleared
+// Layer constants of the parameter set x (2p values, gamma_k and beta_k interleaved) and cleared
 // immediate slots; ends with a barrier.  The caller orders any earlier use of sh before it.
 template <typename R>
 __device__ __forceinline__ void gen_setup(GenShared<R> &sh, const double *x, int p, int t)
