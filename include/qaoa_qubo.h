@@ -205,8 +205,9 @@ qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int 
  * QQ_C128; FP64 diagonal, phase reduction and accumulators).
  *
  * Execution: one launch per cost-diagonal element type present (at most
- * three) drains a queue of (problem, parameter set, pass, tile chunk) items in
- * level-major order from an atomic ticket; a problem with n <= 12 is one item
+ * three) drains a queue of (problem, parameter set, pass, tile chunk) items
+ * from an atomic ticket, ordered by the fraction (j + 1) / L of its problem's
+ * chain of L passes that pass j completes; a problem with n <= 12 is one item
  * per parameter set.  With QQ_C128 the items run the general complex128 pass
  * bodies of qq_evaluate (every problem by tile chunks; for n <= 12 one item of
  * one tile).  Items of a pass wait, bounded in time, for the previous
@@ -223,7 +224,7 @@ qq_status qq_topk(qq_problem *prob, int p, const double *params, int flags, int 
  * QQ_E_NOMEM, QQ_E_DEVICE.
  */
 typedef struct {
-    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: 16 (QQ_C128: 8) */
+    int tiles_per_chunk;   /* tiles (4096 amplitudes) per work item of a multi-pass problem; 0: 24 (QQ_C128: 8) */
     int max_workgroups;    /* cap on the persistent grid; 0: every workgroup that fits on the device at once */
     double wait_limit_ms;  /* bound on one dependency wait; 0: 2000 ms */
 } qq_many_options;
@@ -344,7 +345,7 @@ qq_status qq_evaluate_many_guarded(int count, qq_problem *const *problems, const
  * NULL, appends it to that JSON-lines file; an entry already there for the same
  * device, n, p, batch, planning flags and diagonal width is used without timing.
  * qq_autotune_many does the same for qq_evaluate_many over tiles_per_chunk in
- * {4, 8, 16, 32, 64} and max_workgroups in {0, 2 x compute units}, keyed by a
+ * {4, 8, 16, 24, 32, 48, 64} and max_workgroups in {0, 2 x compute units}, keyed by a
  * hash of every problem's (n, p, batch, diagonal width); it returns the options
  * (to pass to qq_evaluate_many) and the measured time in ms_out (may be NULL).
  * Both allocate their own device memory and synchronise `stream`.

@@ -1090,14 +1090,15 @@ uint64_t fnv1a(uint64_t h, int64_t v)
 
 int many_tiles_per_chunk(uint64_t tiles, const qq_many_options *opt, bool c128)
 {
-    // 16 tiles (512 KiB of one complex64 state) per item: each item ends with an XCD-wide
-    // cache write-back and two device-scope atomics, which a 16-tile item amortises,
-    // while a 2^22-amplitude pass still splits into 64 items (measured on MI355X with
-    // the 512-problem uneven batch: 1 tile 107 ms, 8 tiles 30 ms, 16 and 32 tiles 25 ms).
+    // 24 tiles (768 KiB of one complex64 state) per item: each item ends with an XCD-wide
+    // cache write-back and two device-scope atomics, which such an item amortises, while a
+    // 2^22-amplitude pass still splits into 43 items (measured on MI355X with the 512-problem
+    // uneven batch: 1 tile 107 ms, 8 tiles 30 ms in an earlier version; now 16 tiles 22.0 ms,
+    // 24 20.9, 32 21.1, 48 22.0, 64 23.6).
     // Complex128 (one resident workgroup per compute unit): 8 tiles, so that the longest pass
     // chains split finely (the batch's 88 flagged sets: 2 tiles 13.5 ms, 4 11.4, 8 10.6, 16 11.8,
     // 64 25.5)
-    const uint64_t want = (opt && opt->tiles_per_chunk > 0) ? (uint64_t)opt->tiles_per_chunk : (c128 ? 8 : 16);
+    const uint64_t want = (opt && opt->tiles_per_chunk > 0) ? (uint64_t)opt->tiles_per_chunk : (c128 ? 8 : 24);
     return (int)std::min<uint64_t>(want, tiles);
 }
 
@@ -1107,7 +1108,7 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
     const bool grad = flags & QQ_GRAD;
     const bool c128 = flags & QQ_C128;
     const int mode = plan_mode(flags | QQ_ENERGY, false);
-    // problem order inside each level: longest pass chain first, then most tiles
+    // problem order (the tie-break of the ticket order below): longest pass chain first, then most tiles
     std::vector<int> order(count);
     std::vector<Plan> plans(count);
     for (int i = 0; i < count; ++i) {
@@ -1269,19 +1270,33 @@ qq_status plan_many(int count, qq_problem *const *pbs, const int *p, const int *
             G.inst.push_back(I);
         }
         G.state_bytes = state_off;
-        // level-major segments
-        int max_passes = 0;
-        for (const ManyInst &I : G.inst) max_passes = std::max(max_passes, I.npasses);
+        // segments in the order of the fraction (j + 1) / L of its problem's chain of L passes that
+        // pass j completes (ties: longer chains, then the problem order above): every chain advances
+        // in step with the whole queue, so the long chains do not trail alone at the end, and the
+        // single-item problems (L = 1) come last, where they fill the workgroups the chains leave
+        // idle.  Measured on the 512-problem uneven batch at 32 tiles per item: 21.0 ms against
+        // 22.0 ms level-major (every problem's pass 0, then pass 1, ...).  Pass j of a state always
+        // precedes its pass j + 1, which is all the queue needs.
+        struct SegKey {
+            int num, den, k, b;  // key num / den = (j + 1) / L
+        };
+        std::vector<SegKey> keys;
+        for (size_t k = 0; k < G.inst.size(); ++k)
+            for (int j = 0; j < G.inst[k].npasses; ++j)
+                for (int b = 0; b < G.inst[k].B; ++b) keys.push_back({j + 1, G.inst[k].npasses, (int)k, b});
+        std::sort(keys.begin(), keys.end(), [](const SegKey &x, const SegKey &y) {
+            const int64_t lx = (int64_t)x.num * y.den, ly = (int64_t)y.num * x.den;
+            if (lx != ly) return lx < ly;
+            if (x.den != y.den) return x.den > y.den;
+            if (x.k != y.k) return x.k < y.k;
+            if (x.num != y.num) return x.num < y.num;
+            return x.b < y.b;
+        });
         uint64_t ticket = 0;
-        for (int j = 0; j < max_passes; ++j)
-            for (size_t k = 0; k < G.inst.size(); ++k) {
-                const ManyInst &I = G.inst[k];
-                if (j >= I.npasses) continue;
-                for (int b = 0; b < I.B; ++b) {
-                    G.seg.push_back({(uint32_t)ticket, (uint32_t)k, (uint32_t)b, (uint32_t)j});
-                    ticket += (uint64_t)I.nchunks;
-                }
-            }
+        for (const SegKey &x : keys) {
+            G.seg.push_back({(uint32_t)ticket, (uint32_t)x.k, (uint32_t)x.b, (uint32_t)(x.num - 1)});
+            ticket += (uint64_t)G.inst[x.k].nchunks;
+        }
         if (ticket >= 0xffffffffull) return fail(QQ_E_TOO_LARGE, "%llu work items exceed 2^32", (unsigned long long)ticket);
         G.total = (uint32_t)ticket;
         // workspace regions of the group
@@ -2894,7 +2909,7 @@ qq_status qq_autotune_many(int count, qq_problem *const *problems, const int *p,
     }
     const int eflags = flags | QQ_ENERGY | QQ_PARAMS_ON_DEVICE | QQ_OUT_ON_DEVICE;
     std::vector<qq_many_options> cands;
-    for (int tpc : {4, 8, 16, 32, 64})
+    for (int tpc : {4, 8, 16, 24, 32, 48, 64})
         for (int mw : {0, 2 * cus}) cands.push_back({tpc, mw, 0.0});
     size_t need = 0;
     for (const auto &c : cands) {

@@ -188,9 +188,9 @@ hipError_t static_scratch(int device, void **ptr);
 
 // Persistent launch over many problems (qq_many.hip).
 // Work item = (problem, state b, pass j, chunk c): tiles [c * tpc, min((c + 1) * tpc, tiles))
-// of pass j.  Items are numbered level-major (every problem's pass 0, then every
-// problem's pass 1, ...) and taken in that order from one atomic ticket counter,
-// so an item only ever waits for items with smaller tickets.
+// of pass j.  Items are numbered so that a state's pass j precedes its pass j + 1 (by
+// the fraction of the problem's pass chain done, see plan_many) and taken in that order
+// from one atomic ticket counter, so an item only ever waits for items with smaller tickets.
 struct ManyInst {
     int n, p, B;
     int npasses, pass_off;  // passes in ManyPass[pass_off ..]

@@ -11,9 +11,10 @@
 // (a problem with n <= 12 has one pass of one tile).
 //
 // Ordering and progress.  Tickets are handed out in increasing order from one
-// atomic counter, and items are numbered level-major (pass 0 of every problem,
-// then pass 1, ...), so every item an item waits for has a smaller ticket and
-// is held by a workgroup that is already running.  Hence the queue drains with
+// atomic counter, and items are numbered so that every pass of a state comes
+// after its earlier passes (the host orders them by the fraction of each
+// problem's pass chain done), so every item an item waits for has a smaller
+// ticket and is held by a workgroup that is already running.  Hence the queue drains with
 // any number of resident workgroups.  Every wait is bounded in wall-clock time;
 // a wait that runs out sets an error flag, after which every workgroup stops
 // taking items and the launch ends (the host reports the error).
