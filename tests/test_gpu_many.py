@@ -134,8 +134,10 @@ def test_many_c128_bitwise_across_grids_and_close_across_chunks(mix):
     ea, ga = evaluate_many(pbs, xs, grad=True, c128=True)
     eb, gb = evaluate_many(pbs, xs, grad=True, c128=True, options={"max_workgroups": 5})
     ec, gc = evaluate_many(pbs, xs, grad=True, c128=True, options={"tiles_per_chunk": 1})
+    ed, gd = evaluate_many(pbs, xs, grad=True, c128=True, options={"max_workgroups": 1})
     for k, pb in enumerate(pbs):
         assert np.array_equal(ea[k], eb[k]) and np.array_equal(ga[k], gb[k]), k
+        assert np.array_equal(ea[k], ed[k]) and np.array_equal(ga[k], gd[k]), k
         assert e_err(ec[k], ea[k], pb.info.sigma_c) <= 1e-12, k
         assert g_err(gc[k], ga[k]) <= 1e-12, k
 
@@ -156,9 +158,13 @@ def test_many_bitwise_across_grid_sizes_and_repeat(mix):
     ea, ga = evaluate_many(pbs, xs, grad=True)
     eb, gb = evaluate_many(pbs, xs, grad=True, options={"max_workgroups": 7})
     ec, gc = evaluate_many(pbs, xs, grad=True)
+    # one workgroup takes every item in ticket order: it completes only if every item's
+    # dependencies come earlier in that order (otherwise the bounded wait reports QQ_E_DEVICE)
+    ed, gd = evaluate_many(pbs, xs, grad=True, options={"max_workgroups": 1})
     for k in range(len(pbs)):
         assert np.array_equal(ea[k], eb[k]) and np.array_equal(ga[k], gb[k]), k
         assert np.array_equal(ea[k], ec[k]) and np.array_equal(ga[k], gc[k]), k
+        assert np.array_equal(ea[k], ed[k]) and np.array_equal(ga[k], gd[k]), k
 
 
 def test_many_chunk_sizes_agree(mix):
