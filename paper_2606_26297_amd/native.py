@@ -443,6 +443,36 @@ def qq_evaluate_many_guarded(handles, p, batch, params, flags, opt, tol, energy_
                                           None if rp is None else ctypes.cast(rp, _vp)))
 
 
+def _packed_ptrs(buf, per, esize, name, dtypes):
+    """ctypes array of the start of each problem's block in one packed host buffer: block i holds
+    per[i] elements of esize bytes and starts where block i - 1 ends.  The buffer is checked once."""
+    per = np.asarray(per, dtype=np.int64)
+    base = _host_addr(buf, int(per.sum()) * esize, name, dtypes)
+    starts = base + esize * (np.cumsum(per) - per)
+    return (_vp * len(per))(*starts.tolist())
+
+
+def qq_evaluate_many_guarded_packed(handles, p, batch, params, flags, opt, tol, energy_out, grad_out, c128_out=None,
+                                    grad_err_out=None, stream=None):
+    """qq_evaluate_many_guarded with each kind of buffer packed into one host numpy array, problem after
+    problem: params and grad_out hold batch[i] x 2p[i] doubles per problem, energy_out and grad_err_out
+    batch[i] doubles, c128_out batch[i] int32 (the last two may be None).  One check per array instead
+    of one per problem."""
+    count, hs, pa, ba = _many_arrays(handles, p, batch)
+    n2p, n1 = _need_many(pa, ba, 2) // 8, _need_many(pa, ba, 0, 1) // 8
+    pp = _packed_ptrs(params, n2p, 8, "params", _F64)
+    ep = _packed_ptrs(energy_out, n1, 8, "energy_out", _F64)
+    gp = None if grad_out is None else _packed_ptrs(grad_out, n2p, 8, "grad_out", _F64)
+    cp = None if c128_out is None else _packed_ptrs(c128_out, n1, 4, "c128_out", ("int32",))
+    rp = None if grad_err_out is None else _packed_ptrs(grad_err_out, n1, 8, "grad_err_out", _F64)
+    _check(lib().qq_evaluate_many_guarded(count, ctypes.cast(hs, _vp), pa.ctypes.data_as(_vp), ba.ctypes.data_as(_vp),
+                                          ctypes.cast(pp, _vp), int(flags), _many_options(opt), float(tol),
+                                          _stream_ptr(stream), ctypes.cast(ep, _vp),
+                                          None if gp is None else ctypes.cast(gp, _vp),
+                                          None if cp is None else ctypes.cast(cp, _vp),
+                                          None if rp is None else ctypes.cast(rp, _vp)))
+
+
 def _many_options(opt):
     if opt is None:
         return None

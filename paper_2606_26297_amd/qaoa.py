@@ -180,13 +180,25 @@ def evaluate_many_guarded(problems, params, tol=1e-5, options=None):
     """Energies and gradients of many problems (host numpy lists) with every gradient held to `tol`
     relative: one complex64 persistent launch, then complex128 for the sets whose bound exceeds the
     tolerance.  Returns (energies, gradients, c128 flags, gradient error bounds), each a list."""
-    xs = [np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64) for x in params]
-    e = [np.empty(x.shape[0]) for x in xs]
-    g = [np.empty(x.shape) for x in xs]
-    up = [np.empty(x.shape[0], dtype=np.int32) for x in xs]
-    err = [np.empty(x.shape[0]) for x in xs]
-    N.qq_evaluate_many_guarded([pb.handle for pb in problems], [x.shape[1] // 2 for x in xs], [x.shape[0] for x in xs],
-                               xs, N.QQ_ENERGY | N.QQ_GRAD, options, tol, e, g, up, err)
+    xs = [np.atleast_2d(np.asarray(x, dtype=np.float64)) for x in params]
+    bs = [x.shape[0] for x in xs]
+    ps = [x.shape[1] // 2 for x in xs]
+    # one packed buffer per kind (a check per buffer instead of per problem), split into views after
+    flat = np.concatenate([x.reshape(-1) for x in xs]) if xs else np.empty(0)
+    nb = sum(bs)
+    e_all, g_all = np.empty(nb), np.empty(flat.size)
+    up_all, err_all = np.empty(nb, dtype=np.int32), np.empty(nb)
+    N.qq_evaluate_many_guarded_packed([pb.handle for pb in problems], ps, bs, flat, N.QQ_ENERGY | N.QQ_GRAD, options,
+                                      tol, e_all, g_all, up_all, err_all)
+    e, g, up, err = [], [], [], []
+    o1 = o2 = 0
+    for x, b in zip(xs, bs):
+        e.append(e_all[o1:o1 + b])
+        up.append(up_all[o1:o1 + b])
+        err.append(err_all[o1:o1 + b])
+        g.append(g_all[o2:o2 + x.size].reshape(x.shape))
+        o1 += b
+        o2 += x.size
     return e, g, up, err
 
 

@@ -51,3 +51,25 @@ def test_sample_and_graph_reject_bad_buffers():
         N.qq_sample(None, 2, np.zeros(2), np.full(4, 0.5))
     with pytest.raises(ValueError):  # graph parameters live on the device
         N.qq_graph_create(None, 1, 1, 0, None, np.zeros(2))
+
+
+def test_packed_guarded_buffers_point_at_each_problems_block():
+    # problem i's block starts where block i - 1 ends; the packed wrapper checks each buffer once
+    p, batch = np.array([1, 3, 2], dtype=np.int32), np.array([2, 1, 4], dtype=np.int32)
+    per2p = N._need_many(p, batch, 2) // 8
+    assert per2p.tolist() == [4, 6, 16]
+    buf = np.zeros(int(per2p.sum()))
+    ptrs = N._packed_ptrs(buf, per2p, 8, "params", N._F64)
+    base = buf.__array_interface__["data"][0]
+    assert list(ptrs) == [base, base + 8 * 4, base + 8 * 10]
+    flags = np.zeros(int(batch.sum()), dtype=np.int32)
+    ptrs = N._packed_ptrs(flags, N._need_many(p, batch, 0, 1) // 8, 4, "c128_out", ("int32",))
+    base = flags.__array_interface__["data"][0]
+    assert list(ptrs) == [base, base + 4 * 2, base + 4 * 3]
+    with pytest.raises(ValueError):  # one double short
+        N._packed_ptrs(np.zeros(25), per2p, 8, "params", N._F64)
+    with pytest.raises(TypeError):
+        N._packed_ptrs(np.zeros(26, dtype=np.float32), per2p, 8, "params", N._F64)
+    with pytest.raises(ValueError):  # the whole guarded call refuses a short packed output before any library call
+        N.qq_evaluate_many_guarded_packed([None] * 3, p, batch, np.zeros(26), E | N.QQ_GRAD, None, 1e-5,
+                                          np.zeros(6), np.zeros(26))
