@@ -303,7 +303,8 @@ qq_status qq_evaluate_guarded(qq_problem *prob, int p, int batch, const double *
                               double *grad_err_out);
 
 /* The same for many problems: complex64 through one persistent launch (qq_evaluate_many), then the
- * sets whose bound exceeds the tolerance through a second one with complex128 states (QQ_C128).
+ * sets whose bound exceeds the tolerance through a second one with complex128 states (QQ_C128), or
+ * through the per-pass complex128 kernels when they all belong to one problem.
  * c128_out[i] and grad_err_out[i] (each array may be NULL, or hold NULL entries) have batch[i]
  * entries.  QQ_C128 and QQ_PARTITIONED are not accepted (QQ_E_UNSUPPORTED). */
 qq_status qq_evaluate_many_guarded(int count, qq_problem *const *problems, const int *p, const int *batch,

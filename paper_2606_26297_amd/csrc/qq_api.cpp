@@ -1391,18 +1391,23 @@ struct SideStreams {
 };
 
 // Recompute every job's sets with complex128 states (host in, host out; all problems on one device).
-// Monolithic phases: one persistent complex128 launch (qq_evaluate_many) over all of them.
-// Partitioned phases: the parameters go to the device in one copy; the jobs then run round-robin on
-// up to kC128Streams streams of their own, each with its own workspace (the largest any job needs),
-// so that the small per-problem launches of different problems overlap; one device output buffer is
-// read back after all of them.
+// Several problems with monolithic phases: one persistent complex128 launch (qq_evaluate_many) over
+// all of them (the uneven batch's 88 flagged sets: 10.6 ms against about 20 ms of per-problem
+// launches).  One problem, or partitioned phases: per-problem evaluations with the per-pass kernels,
+// which are faster for a single problem (n = 26, p = 4, 8 sets: 175 ms against 200-219 ms through
+// the persistent launch; n = 20, one set: 0.3 against 1.1 ms).  Their parameters go to the device in
+// one copy; the jobs run round-robin on up to kC128Streams streams of their own, each with its own
+// workspace (the largest any job needs), so that the small per-problem launches of different
+// problems overlap; one device output buffer is read back after all of them.
 constexpr int kC128Streams = 4;
 
 qq_status recompute_c128(std::vector<C128Job> &jobs, int flags, void *stream_)
 {
     const int f = (flags & (QQ_ENERGY | QQ_GRAD | QQ_PARTITIONED)) | QQ_C128;
     const bool grad = flags & QQ_GRAD;
-    if (!(f & QQ_PARTITIONED)) {
+    int with_sets = 0;
+    for (const C128Job &j : jobs) with_sets += j.sets.empty() ? 0 : 1;
+    if (!(f & QQ_PARTITIONED) && with_sets > 1) {
         // every recomputed set in one persistent complex128 launch (per cost-diagonal element type)
         std::vector<qq_problem *> pbs;
         std::vector<int> ps, bs;
@@ -1445,7 +1450,7 @@ qq_status recompute_c128(std::vector<C128Job> &jobs, int flags, void *stream_)
         }
         return QQ_OK;
     }
-    // partitioned phases: per-problem evaluations spread over side streams
+    // one problem, or partitioned phases: per-problem evaluations spread over side streams
     size_t wsmax = 0, nx = 0, nout = 0;
     int nj = 0;
     for (const C128Job &j : jobs) {

@@ -1,9 +1,9 @@
 """The guarded evaluation calls (qq_evaluate_guarded, qq_evaluate_many_guarded) through the C ABI.
 
 Each returned gradient must be within tol of the FP64 oracle's, relative to ||g||_inf with no floor,
-and within the returned bound; sets kept in complex64 equal qq_evaluate's results bit for bit, sets
-flagged complex128 equal the per-pass complex128 path's to 1e-12 (they are recomputed by the persistent
-complex128 launch, which sums its FP64 partials in another order).  Covered: a set with a tiny gradient (forced to
+and within the returned bound; sets kept in complex64 equal qq_evaluate's results bit for bit, and for
+one problem the sets flagged complex128 equal the per-pass complex128 path's (many problems recompute
+theirs in one persistent complex128 launch, held to the oracle here and in the persistent-launch tests).  Covered: a set with a tiny gradient (forced to
 complex128) next to ordinary ones, the partitioned mode, QQ_C128 (every set complex128), energy only
 (nothing recomputed), a tighter tolerance, and the argument checks.
 """
@@ -47,12 +47,8 @@ def test_guarded_mixes_complex64_and_complex128_sets():
         e64, g64 = pb.evaluate(x, grad=True)
         e128, g128 = pb.evaluate(x[up == 1], grad=True, c128=True)
         assert np.array_equal(e[up == 0], e64[up == 0]) and np.array_equal(g[up == 0], g64[up == 0])
-        # recomputed sets: the persistent complex128 launch, the same arithmetic per amplitude as the
-        # per-pass complex128 kernels with the FP64 partial sums in another order
-        sig = pb.info.sigma_c
-        assert np.max(np.abs(e[up == 1] - e128) / np.maximum(np.abs(e128), sig)) <= 1e-12
-        for a, r in zip(g[up == 1], g128):
-            assert np.max(np.abs(a - r)) <= 1e-12 * np.max(np.abs(r))
+        # one problem: its flagged sets are recomputed by the per-pass complex128 kernels
+        assert np.array_equal(e[up == 1], e128) and np.array_equal(g[up == 1], g128)
         check_against_oracle(inst, x, e, g, err, 1e-5, pb.info.sigma_c)
     finally:
         pb.close()
