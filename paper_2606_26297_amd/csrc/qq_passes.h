@@ -532,8 +532,8 @@ __device__ __forceinline__ uint32_t part_gather(uint64_t zb, uint64_t vmask)
 }
 
 // The phase of the partitioned cost for this thread's 16 registers, as angles in revolutions:
-// uf[r] = the sum over the local factors and the cross factor of (gamma / 2 pi) C_m(z), each
-// term reduced on its own in FP64 to [-1/2, 1/2], the sum reduced again and rounded to float.
+// uf[r] = (gamma / 2 pi) times the FP64 sum over the local factors and the cross factor of C_m(z),
+// reduced in FP64 to [-1/2, 1/2] and rounded to float (the product of the factors as one rotation).
 // Layout: lanes hold qubits 0..3 (lane_lo) and qh, qh + 1 (lane_hi); registers hold qubits
 // qr..qr+3; zb is the tile's wave-uniform first index, `tile` its index in the pass's table.  Every
 // factor is quadratic in z, so its 16 register values follow from its value at register 0, its four
@@ -559,7 +559,7 @@ __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &
     cdouble_t *xu = (cdouble_t *)xrow;
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(t >> 6);
     // one factor's value at register 0 of half h (v0) and its four register increments k -> its 8
-    // register values of half h, reduced and added to u
+    // register values of half h, added to the FP64 sums u of the factors' values
     auto add_factor = [&](double v0, const double (&k)[4], RegQ *w, int h, double (&u)[H], bool first) {
         double v[H];
         v[0] = v0;
@@ -569,10 +569,7 @@ __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &
             v[i] = (v[i - (1 << j)] + k[j]) + w[h * H + i];
         }
 #pragma unroll
-        for (int i = 0; i < H; ++i) {
-            const double x = g2pi * v[i];
-            u[i] = first ? x - rint(x) : u[i] + (x - rint(x));
-        }
+        for (int i = 0; i < H; ++i) u[i] = first ? v[i] : u[i] + v[i];
     };
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -602,8 +599,12 @@ __device__ __forceinline__ void part_angles(float (&uf)[kRegs], const FastArgs &
             for (int j = 0; j < 4; ++j) k[j] = e[j + 1] - e[0];
             add_factor(h ? e[4] : e[0], k, pcq + ((size_t)m * a.pcq_runs + qr) * kRegs, h, u, false);
         }
+        // one argument per amplitude: (gamma / 2 pi) times the sum of the factors' values, reduced
 #pragma unroll
-        for (int i = 0; i < H; ++i) uf[h * H + i] = (float)(u[i] - rint(u[i]));
+        for (int i = 0; i < H; ++i) {
+            const double x = g2pi * u[i];
+            uf[h * H + i] = (float)(x - rint(x));
+        }
     }
 }
 
