@@ -244,31 +244,35 @@ def _label(name, index):
     return name if index is None else f"{name}[{index}]"
 
 
+def _dev_addr(x, nbytes, name, dtypes, index=None):
+    """Address of a contiguous CUDA tensor of an accepted element type holding at least nbytes."""
+    if not getattr(x, "is_cuda", False):
+        raise ValueError(f"{_label(name, index)}: a CUDA tensor is required with the *_ON_DEVICE flag")
+    if not x.is_contiguous():
+        raise ValueError(f"{_label(name, index)}: the tensor must be contiguous")
+    size = x.numel() * x.element_size()
+    if dtypes is not None:
+        dt = str(x.dtype).replace("torch.", "")
+        if dt not in dtypes:
+            raise TypeError(f"{_label(name, index)}: element type {dt}, expected one of {', '.join(dtypes)}")
+    if size < nbytes:
+        raise ValueError(f"{_label(name, index)}: holds {size} bytes, {nbytes} needed")
+    return int(x.data_ptr())
+
+
 def _buf(x, nbytes, name, device, dtypes=None):
     """Address of a caller buffer after checking it: a contiguous CUDA tensor (device) or a
     C-contiguous numpy array (host) of an accepted element type holding at least nbytes.  A short or
     strided buffer would otherwise be read or written out of bounds by the library."""
-    if not device:
-        return ctypes.c_void_p(_host_addr(x, nbytes, name, dtypes))
-    if not getattr(x, "is_cuda", False):
-        raise ValueError(f"{name}: a CUDA tensor is required with the *_ON_DEVICE flag")
-    if not x.is_contiguous():
-        raise ValueError(f"{name}: the tensor must be contiguous")
-    size, dt, addr = x.numel() * x.element_size(), str(x.dtype).replace("torch.", ""), int(x.data_ptr())
-    if dtypes is not None and dt not in dtypes:
-        raise TypeError(f"{name}: element type {dt}, expected one of {', '.join(dtypes)}")
-    if size < nbytes:
-        raise ValueError(f"{name}: holds {size} bytes, {nbytes} needed")
+    addr = _dev_addr(x, nbytes, name, dtypes) if device else _host_addr(x, nbytes, name, dtypes)
     return ctypes.c_void_p(addr)
 
 
 def _bufs(xs, sizes, name, device, dtypes=None):
     """ctypes array of the addresses of one buffer per problem, each checked as _buf checks one."""
     sizes = [int(v) for v in sizes]
-    if device:
-        addrs = [_buf(x, sizes[i], f"{name}[{i}]", True, dtypes).value for i, x in enumerate(xs)]
-    else:
-        addrs = [_host_addr(x, sizes[i], name, dtypes, i) for i, x in enumerate(xs)]
+    check = _dev_addr if device else _host_addr
+    addrs = [check(x, sizes[i], name, dtypes, i) for i, x in enumerate(xs)]
     return (_vp * len(addrs))(*addrs)
 
 
