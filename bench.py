@@ -806,6 +806,8 @@ def main():
                     help="with --uneven-only: only the guarded evaluation (complex64 launch, complex128 recomputation)")
     ap.add_argument("--persistent-only", action="store_true",
                     help="with --uneven-only: time only the persistent launch (no per-problem launches)")
+    ap.add_argument("--multi-qpu-only", action="store_true",
+                    help="run only the n = 32 multi-QPU leg (monolithic and partitioned phases)")
     ap.add_argument("--aux-only", action="store_true",
                     help="run only the cost-diagonal / probabilities / top-k leg on the timed instance")
     ap.add_argument("--no-host-buffers", action="store_true",
@@ -844,7 +846,7 @@ def main():
     from paper_2606_26297_amd.qaoa import Problem
 
     oracle_cores = None
-    if not (args.no_cpu_baseline or args.uneven_only or args.aux_only):
+    if not (args.no_cpu_baseline or args.uneven_only or args.aux_only or args.multi_qpu_only):
         progress("oracle on several cores (before the GPU is touched)")
         oracle_cores = oracle_multicore_uneven()
 
@@ -866,6 +868,13 @@ def main():
         progress("cost diagonal, probabilities, top-k")
         inst, x = W.workload3(batch=1, p=args.p, n=args.n)
         res = {"aux": aux_kernels(dev, inst, x)}
+        if args.copy_calibration:
+            res["copy_calibration"] = copy_calibration(dev)
+        print(json.dumps(res), flush=True)
+        return
+    if args.multi_qpu_only:
+        progress("n = 32 multi-QPU workload")
+        res = {"multi_qpu": multi_qpu(dev)}
         if args.copy_calibration:
             res["copy_calibration"] = copy_calibration(dev)
         print(json.dumps(res), flush=True)
